@@ -1,0 +1,118 @@
+"""Whole-image transfer energy and its hand-derived gradient, FP64 (TEST INFRASTRUCTURE ONLY).
+
+Definitions followed (Sec. 3.1, Sec. 4.2):
+
+* features V^L(x): post-ReLU activation of the named conv, reshaped n_p x n_c
+* Gram (Sec. 3.1):            G^L(x) = V^T V / n_p, n_p = h_L * w_L of the whole image
+* style energy (Eq. 2-3):     E_style = sum_L w_L || G^L(x) - G^L(v) ||_F^2
+* content energy (Sec. 3.1):  E_content = lambda_c || V^{Lc}(x) - V^{Lc}(u) ||^2
+* transfer energy (Eq. 1):    E = E_content + E_style
+* feature gradients (Table 1): MSE row  dE/dV = 2 (V - V_ref) (times lambda_c);
+  Gram row written without assuming symmetry, dE/dV = (2 w / n_p) V (D + D^T)
+  with D = G - G_ref, which equals the printed (4 w / n_p) V D when D is symmetric.
+* backward: reverse layer loop with ReLU'(0) = 0, max-pool routing to the
+  first maximum, conv adjoint.
+
+Arrays are C x H x W float64; V in the paper's n_p x n_c orientation is the
+transpose of the C x (H W) reshape used here.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .net import NetSpec
+from .ops import conv3x3, conv3x3_adjoint, maxpool2, maxpool2_backward, relu
+
+
+def last_needed(net: NetSpec) -> int:
+    return max(list(net.style) + ([net.content] if net.content is not None else []))
+
+
+def forward(net: NetSpec, x: np.ndarray, ws, bs, upto: int | None = None):
+    """Post-ReLU activation A_i of every conv i <= upto (pre-pool)."""
+    if upto is None:
+        upto = last_needed(net)
+    a = np.asarray(x, np.float64)
+    acts = []
+    for i in range(upto + 1):
+        z = conv3x3(a, ws[i], bs[i])
+        ai = relu(z)
+        acts.append(ai)
+        a = maxpool2(ai) if i in net.pool_after else ai
+    return acts
+
+
+def gram(v: np.ndarray, n_p: int) -> np.ndarray:
+    """G = V^T V / n_p for a C x h x w feature map (V is (h w) x C)."""
+    c = v.shape[0]
+    m = v.reshape(c, -1)
+    return (m @ m.T) / float(n_p)
+
+
+def content_features(net: NetSpec, c_img: np.ndarray, ws, bs) -> np.ndarray:
+    assert net.content is not None
+    return forward(net, c_img, ws, bs, upto=net.content)[net.content]
+
+
+def style_grams(net: NetSpec, s_img: np.ndarray, ws, bs):
+    acts = forward(net, s_img, ws, bs, upto=max(net.style))
+    return [gram(acts[i], acts[i].shape[1] * acts[i].shape[2]) for i in net.style]
+
+
+def energy_terms(grams_x, grams_t, w_style, e_content):
+    """Per-layer style terms w_L ||G_x - G_t||_F^2 and the total (Eq. 1-3)."""
+    e_style = [float(wl * np.sum((gx - gt) ** 2)) for gx, gt, wl in zip(grams_x, grams_t, w_style)]
+    return {"E": float(e_content + sum(e_style)), "E_content": float(e_content), "E_style": e_style}
+
+
+def style_seed(v: np.ndarray, g: np.ndarray, g_t: np.ndarray, w_l: float, n_p: int) -> np.ndarray:
+    """Gram row of Table 1 on a C x h x w map: (2 w / n_p) V (D + D^T), D = G - G_t."""
+    c = v.shape[0]
+    d = g - g_t
+    return ((2.0 * w_l / n_p) * ((d + d.T) @ v.reshape(c, -1))).reshape(v.shape)
+
+
+def content_seed(v: np.ndarray, f_ref: np.ndarray, alpha: float) -> np.ndarray:
+    """MSE row of Table 1 times lambda_c: 2 alpha (V - V_ref)."""
+    return 2.0 * alpha * (v - f_ref)
+
+
+def backward(net: NetSpec, acts, seeds: dict, ws) -> np.ndarray:
+    """Reverse pass: seeds[i] is dE/dA_i added at conv i's ReLU output; returns dE/dx."""
+    top = len(acts) - 1
+    g = None
+    for i in range(top, -1, -1):
+        da = np.zeros_like(acts[i]) if g is None else g
+        if i in seeds:
+            da = da + seeds[i]
+        dz = np.where(acts[i] > 0.0, da, 0.0)          # ReLU'(0) = 0
+        dx = conv3x3_adjoint(dz, ws[i])
+        if i > 0 and (i - 1) in net.pool_after:
+            g = maxpool2_backward(dx, acts[i - 1])
+        else:
+            g = dx
+    return g
+
+
+def loss_grad(net: NetSpec, x, ws, bs, grams_t, f_c, w_style, alpha, want_grad=True):
+    """Whole-image E (with terms), Grams of x and dE/dx (Eq. 1-3, Table 1)."""
+    acts = forward(net, x, ws, bs)
+    grams_x, n_ps = [], []
+    for i in net.style:
+        n_p = acts[i].shape[1] * acts[i].shape[2]
+        n_ps.append(n_p)
+        grams_x.append(gram(acts[i], n_p))
+    e_c = 0.0
+    if net.content is not None and alpha != 0.0:
+        e_c = float(alpha * np.sum((acts[net.content] - f_c) ** 2))
+    terms = energy_terms(grams_x, grams_t, w_style, e_c)
+    terms["grams"] = grams_x
+    if not want_grad:
+        return terms, None
+    seeds = {}
+    for k, i in enumerate(net.style):
+        seeds[i] = style_seed(acts[i], grams_x[k], grams_t[k], w_style[k], n_ps[k])
+    if net.content is not None and alpha != 0.0:
+        cs = content_seed(acts[net.content], f_c, alpha)
+        seeds[net.content] = seeds.get(net.content, 0.0) + cs
+    return terms, backward(net, acts, seeds, ws)
