@@ -1,0 +1,161 @@
+/*
+ * nst.h -- C ABI of the localized style-transfer loss+gradient library (libnst.so)
+ *
+ * Method: Galerne, Raad, Lezama, Morel, "Scaling Painting Style Transfer".
+ *   Energy (Eq. 1-3):   E(x) = sum_l w_l || G_l(x) - G_l(s) ||_F^2 + alpha || F(x) - F(c) ||^2
+ *   Gram (Sec. 3.1):    G_l = V_l^T V_l / n_p^l, V_l the n_p^l x C_l post-ReLU features of
+ *                       conv k_1 (style layers), n_p^l the whole-image feature-pixel count
+ *   Feature gradients:  Table 1 (Gram row and MSE row)
+ *   Localized passes:   Sec. 4.1 (blocks with margin) and Algorithm 1 (Step 1 global
+ *                       statistics block by block, Step 2 per-block backward that keeps the
+ *                       inner part of the gradient)
+ *
+ * Conventions shared by every entry point
+ *   - Images are device pointers to float32, planar C x H x W (C = 3), row-major.
+ *   - Gram matrices are device pointers to float64: the style layers in network order,
+ *     each C_l x C_l row-major, concatenated, already divided by n_p^l of the image they
+ *     were computed on.
+ *   - Feature maps are device pointers to float32, h x w x C (channels fastest), where
+ *     h = floor(H / s), w = floor(W / s) and s is the layer's cumulative pooling stride.
+ *   - The caller owns every input and output buffer.  The context owns only its packed
+ *     copy of the network weights.  Scratch memory is a caller-provided device workspace
+ *     sized with nst_workspace_bytes(); the run calls allocate nothing.
+ *   - All device work is enqueued on `stream` (a hipStream_t; NULL is the null stream).
+ *     Calls return after enqueueing, except that a non-NULL host `energy` output makes
+ *     the call wait for the stream to copy the energies back.
+ *   - Every call validates its arguments before launching anything; on a validation
+ *     error no output is touched.  A HIP runtime failure returns NST_EHIP and leaves the
+ *     outputs undefined.  Nothing aborts or throws across the ABI.
+ *   - A context is not thread-safe: use one context per host thread / stream.
+ *   - Tile plan (block T, margin m): see nst_plan().  Results equal the whole-image ones
+ *     (up to rounding) when m >= nst_min_halo(); smaller margins are accepted unless
+ *     NST_STRICT_HALO is set, so that the margin-too-small seams can be reproduced.
+ */
+#ifndef NST_H
+#define NST_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NST_ABI_VERSION 1
+#define NST_MAX_CONV 16
+#define NST_MAX_STYLE 8
+
+typedef struct nst_ctx nst_ctx;
+
+typedef enum {
+  NST_OK = 0,
+  NST_EINVAL = -1,      /* NULL pointer, bad enum/flag, unsupported network shape       */
+  NST_ESHAPE = -2,      /* H, W, T < 1, m < 0, or an image too large for 32-bit indexing */
+  NST_EHALO = -3,       /* m < nst_min_halo() under NST_STRICT_HALO                      */
+  NST_ENOMEM = -4,      /* nst_create could not allocate the packed weights              */
+  NST_EHIP = -5,        /* a HIP runtime call failed                                      */
+  NST_ECAPACITY = -6,   /* nst_plan: output array too small (needed count is returned)  */
+  NST_EWORKSPACE = -7   /* workspace smaller than nst_workspace_bytes(..., tile_batch=1) */
+} nst_status;
+
+typedef enum { NST_FP32 = 0, NST_BF16 = 1 } nst_precision;
+
+enum {
+  NST_STEP1 = 1,        /* Algorithm 1 Step 1: global Grams of x (+ energies)            */
+  NST_STEP2 = 2,        /* Algorithm 1 Step 2: gradient from given Grams of x            */
+  NST_BOTH = 3,
+  NST_STRICT_HALO = 4   /* reject m < nst_min_halo()                                      */
+};
+
+/* A VGG-style feature network: n_conv 3x3 convs (zero padding 1, stride 1), each followed
+ * by ReLU, some followed by a 2x2 stride-2 floor-mode max pool.  Style layers and the
+ * content layer name convs whose post-ReLU (pre-pool) output is used.  Supported shapes:
+ * c_in[0] == 3; c_in[i] == c_out[i-1]; c_out[i] a multiple of 32; a style layer is not
+ * followed by a pool unless it is the last conv; the last conv is a style or content layer. */
+typedef struct {
+  int n_conv;
+  int c_in[NST_MAX_CONV];
+  int c_out[NST_MAX_CONV];
+  unsigned pool_after;            /* bit i set: max pool after conv i                    */
+  int n_style;
+  int style_conv[NST_MAX_STYLE];  /* increasing conv indices                              */
+  int content_conv;               /* conv index, or -1 (no content term)                  */
+} nst_net_desc;
+
+/* One block of the plan.  Image-pixel coordinates, half-open. */
+typedef struct {
+  int by0, by1, bx0, bx1;         /* the block (inner part) this tile owns                 */
+  int ey0, ey1, ex0, ex1;         /* its window: block + margin, aligned, clipped          */
+  int own[NST_MAX_CONV][4];       /* owned feature rows/cols (r0, r1, c0, c1) of each conv */
+} nst_tile;
+
+int nst_abi_version(void);
+const char *nst_strerror(int status);
+
+/* Fill `out` with the VGG-19 prefix conv1_1..conv5_1 (tiny != 0: conv1_1..conv3_1).
+ * Style layers relu{1..5}_1 (tiny: relu1_1, relu2_1, relu3_1); content relu4_2
+ * (tiny: relu2_2) or none when with_content == 0.  Sec. 3.1 names these layers. */
+int nst_net_vgg19(nst_net_desc *out, int tiny, int with_content);
+
+/* Smallest margin that makes the tiled Grams and gradient exact: the widest receptive
+ * field, max_i (a_i + b_i), where feature row q of conv i depends on input rows
+ * [s_i q - a_i, s_i q + b_i] (Sec. 4.1: margin must cover the receptive field).
+ * Returns a negative nst_status on an invalid descriptor.  Host only. */
+int nst_min_halo(const nst_net_desc *net);
+
+/* The tile plan (Sec. 4.1, Algorithm 1).  Blocks: row-major grid, rows [i T, min((i+1) T, H)).
+ * Window: [S floor((b0 - m) / S), S ceil((b1 + m) / S)) clipped to the image, S = product of
+ * the pooling factors.  Owned feature rows of conv i (stride s): [ceil(b0/s), min(ceil(b1/s),
+ * floor(H/s))); columns likewise.  Writes min(cap, count) tiles to `out` (may be NULL when
+ * cap == 0) and the count to *n_tiles; returns NST_ECAPACITY if cap < count.  Host only. */
+int nst_plan(const nst_net_desc *net, int H, int W, int T, int m,
+             nst_tile *out, int cap, int *n_tiles);
+
+/* Device workspace needed to process `tile_batch` tiles of the plan at once with the given
+ * precision; the run calls use the largest batch that fits in what they are given.  Host only. */
+int nst_workspace_bytes(const nst_net_desc *net, int precision, int H, int W, int T, int m,
+                        int tile_batch, size_t *bytes);
+
+/* Create a context on the current HIP device.  w[i]: host float32 [c_out][c_in][3][3];
+ * b[i]: host float32 [c_out] or NULL for zero bias.  Packs device copies. */
+int nst_create(const nst_net_desc *net, const float *const *w, const float *const *b,
+               int precision, nst_ctx **out);
+void nst_destroy(nst_ctx *ctx);
+
+/* Global style Grams of image s (3 x H x W), computed block by block (Algorithm 1 Require:
+ * statistics of the style image "computed block by block").  grams: device float64 output,
+ * sum_l C_l^2 values. */
+int nst_style_grams(nst_ctx *ctx, const float *s, int H, int W, int T, int m, double *grams,
+                    void *ws, size_t ws_bytes, void *stream);
+
+/* Post-ReLU features of conv `conv` for image img, computed block by block and written to
+ * the whole-image map feats (device float32, h x w x C_conv).  With conv == content_conv
+ * this is the content-feature input of Algorithm 1. */
+int nst_layer_feats(nst_ctx *ctx, const float *img, int H, int W, int T, int m, int conv,
+                    float *feats, void *ws, size_t ws_bytes, void *stream);
+
+/* Content features V^{Lc}(c) (Algorithm 1 Require) = nst_layer_feats at content_conv. */
+int nst_content_feats(nst_ctx *ctx, const float *c, int H, int W, int T, int m, float *feats,
+                      void *ws, size_t ws_bytes, void *stream);
+
+/* Algorithm 1 on x (3 x H x W).
+ *   target_grams : device float64, Grams of the style image (nst_style_grams layout)
+ *   content_feats: device float32 content features of the content image at H x W, or NULL
+ *                  iff alpha == 0 or the network has no content layer
+ *   w_style      : host float64 [n_style], the w_l of Eq. 3
+ *   flags        : NST_STEP1 | NST_STEP2 (| NST_STRICT_HALO)
+ *   grams_x      : device float64; written by Step 1; read by Step 2 when Step 1 is not
+ *                  requested (the autograd backward reuses the forward's Grams)
+ *   energy       : host float64 [2 + n_style] = {E, E_content, E_style_l...} or NULL.
+ *                  E_content is summed over owned content features of whichever passes ran.
+ *   grad         : device float32 3 x H x W, dE/dx, written when NST_STEP2 is set.
+ * Memory: one tile batch's activations plus the Grams; nothing whole-image besides the
+ * inputs and outputs. */
+int nst_loss_grad(nst_ctx *ctx, const float *x, int H, int W, const double *target_grams,
+                  const float *content_feats, const double *w_style, double alpha, int T,
+                  int m, int flags, double *grams_x, double *energy, float *grad, void *ws,
+                  size_t ws_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NST_H */

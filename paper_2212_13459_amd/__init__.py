@@ -1,0 +1,8 @@
+"""Localized (tiled, two-pass) style-transfer loss and gradient on MI355X (gfx950).
+
+The compute path is libnst.so (hand-written HIP kernels behind a C ABI, declared in
+include/nst.h).  ``nst`` is the thin Python binding; it refuses to run without the
+built library.
+"""
+from .nst import (NST_BOTH, NST_STEP1, NST_STEP2, NST_STRICT_HALO, Context, StyleEnergy,  # noqa: F401
+                  min_halo, plan, vgg19_desc, workspace_bytes)

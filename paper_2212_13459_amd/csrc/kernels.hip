@@ -1,0 +1,730 @@
+// gfx950 kernels of the localized style-transfer loss and gradient.
+//
+// Layout: activations are NHWC per tile window (channels fastest), one workspace slot
+// per tile of a batch.  Every kernel takes a Batch (per-tile geometry by value) and maps
+// blockIdx.x to (tile, work block) through the Batch prefix sums, so one launch covers
+// all tiles of a batch, ragged or not.
+//
+// Numerics: FP32 accumulation everywhere (MFMA f32 accumulators); FP64 for Gram
+// partial reductions across chunks/tiles and for all energy sums.  All reductions run
+// in a fixed order, so results are bitwise reproducible and independent of the batch
+// size.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kernels.h"
+
+namespace nst {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// CK: input channels staged per LDS chunk (64 bytes per pixel for both precisions).
+template <typename T> struct Tr;
+template <> struct Tr<float> { static constexpr int CK = 16; };
+template <> struct Tr<bf16> { static constexpr int CK = 32; };
+
+__device__ __forceinline__ float to_f(float v) { return v; }
+__device__ __forceinline__ float to_f(bf16 v) { return (float)v; }
+template <typename T> __device__ __forceinline__ T from_f(float v);
+template <> __device__ __forceinline__ float from_f<float>(float v) { return v; }
+template <> __device__ __forceinline__ bf16 from_f<bf16>(float v) { return (bf16)v; }
+
+// One lane's operand fragment: the CK/2 consecutive channels of its k-half.
+// The 32x32 MFMAs pair A-lane (row m, k-half g, element j) with B-lane (col n, g, j),
+// so any assignment of channels to (g, j) that A and B share gives the same sum.
+template <typename T> struct Mma;
+template <> struct Mma<float> {
+  struct Frag { f32x4 v[2]; };
+  static __device__ __forceinline__ Frag load(const float *p) {
+    Frag f;
+    f.v[0] = *(const f32x4 *)p;
+    f.v[1] = *(const f32x4 *)(p + 4);
+    return f;
+  }
+  static __device__ __forceinline__ void mma(f32x16 &acc, const Frag &a, const Frag &b) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.v[h][j], b.v[h][j], acc, 0, 0, 0);
+  }
+};
+template <> struct Mma<bf16> {
+  struct Frag { bf16x8 v[2]; };
+  static __device__ __forceinline__ Frag load(const bf16 *p) {
+    Frag f;
+    f.v[0] = *(const bf16x8 *)p;
+    f.v[1] = *(const bf16x8 *)(p + 8);
+    return f;
+  }
+  static __device__ __forceinline__ void mma(f32x16 &acc, const Frag &a, const Frag &b) {
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.v[0], b.v[0], acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.v[1], b.v[1], acc, 0, 0, 0);
+  }
+};
+
+__device__ __forceinline__ int find_tile(const Batch &g, int bid) {
+  int t = 0;
+  while (t + 1 < g.n && bid >= g.pfx[t + 1]) ++t;
+  return t;
+}
+
+// ---------------------------------------------------------------------------------------
+// Implicit-GEMM 3x3 convolution on MFMA.
+//   M = output pixels of a PH x 16 spatial patch, N = BN output channels, K = taps x cin.
+//   Segment 0: the 9 taps over `in` (halo patch staged in LDS) or, for the image input,
+//              an im2col of the 27 (tap, colour) values padded to 32.
+//   Segment 1: the centre tap over `in2` (the style residual V D~ of the data gradient).
+//   Epilogues: forward bias+ReLU (+ fp32 content difference), backward content residual
+//   + ReLU mask, or the image-gradient stitch of the block's inner pixels.
+// 256 threads = 4 waves in a WM x WN grid, each wave TM x TN blocks of 32x32.
+// ---------------------------------------------------------------------------------------
+template <typename T, int PH, int BN, int WM, int WN, int IN, int EPI, bool SEG2>
+__global__ __launch_bounds__(256) void k_conv(ConvArgs a, Batch g) {
+  constexpr int PW = 16, BM = PH * PW;
+  constexpr int TM = BM / (WM * 32), TN = BN / (WN * 32);
+  static_assert(WM * WN == 4 && TM >= 1 && TN >= 1, "bad wave tiling");
+  constexpr int CK = Tr<T>::CK;
+  constexpr int VEC = 16 / sizeof(T);
+  constexpr int ST = CK + VEC;                       // LDS row stride: 16-byte pad
+  constexpr int HP = PH + 2, WP = PW + 2;
+  constexpr int APIX = (IN == IN_IMAGE) ? BM : HP * WP;
+  constexpr int NTAPB = (IN == IN_NHWC) ? 9 : 1;
+  __shared__ __attribute__((aligned(16))) T As[APIX * ST];
+  __shared__ __attribute__((aligned(16))) T Bs[NTAPB * BN * ST];
+
+  const int t = find_tile(g, blockIdx.x);
+  const int lb = blockIdx.x - g.pfx[t];
+  const int h = g.h[t], w = g.w[t];
+  const int nbx = (w + PW - 1) / PW;
+  const int y0 = (lb / nbx) * PH, x0 = (lb % nbx) * PW;
+  const int n0 = blockIdx.y * BN;
+  const long long slot = g.slot[t];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  const int l32 = lane & 31, half = lane >> 5;
+
+  int pidx[TM];
+#pragma unroll
+  for (int tm = 0; tm < TM; ++tm) {
+    const int m = wm * TM * 32 + tm * 32 + l32;
+    pidx[tm] = (IN == IN_IMAGE) ? m : (m / PW) * WP + (m % PW);
+  }
+
+  f32x16 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+#pragma unroll 1
+  for (int seg = 0; seg < 2; ++seg) {
+    if (seg == 0 && IN == IN_NONE) continue;
+    if (seg == 1 && !SEG2) continue;
+    const T *src = (const T *)(seg == 0 ? a.in : a.in2);
+    const long long ss = seg == 0 ? a.in_ss : a.in2_ss;
+    const int cin = seg == 0 ? (IN == IN_IMAGE ? 32 : a.cin) : a.cin2;
+    const T *wsrc = (const T *)(seg == 0 ? a.wp : a.wp2);
+    const int ntap = (seg == 0 && IN == IN_NHWC) ? 9 : 1;
+    const int nck = cin / CK;
+    const T *base = (seg == 0 && IN == IN_IMAGE) ? nullptr : src + slot * ss;
+
+#pragma unroll 1
+    for (int ck = 0; ck < nck; ++ck) {
+      __syncthreads();
+      if (seg == 0 && IN == IN_IMAGE) {
+        for (int e = tid; e < BM * CK; e += 256) {
+          const int m = e / CK, kk = e - m * CK, k = ck * CK + kk;
+          const int py = y0 + m / PW, px = x0 + m % PW;
+          float v = 0.f;
+          if (k < 27 && py < h && px < w) {
+            const int tap = k / 3, c = k - tap * 3;
+            const int yy = py + tap / 3 - 1, xx = px + tap % 3 - 1;
+            if (yy >= 0 && yy < h && xx >= 0 && xx < w)
+              v = a.img[((long long)c * a.img_h + (g.gy[t] + yy)) * a.img_w + (g.gx[t] + xx)];
+          }
+          As[m * ST + kk] = from_f<T>(v);
+        }
+      } else {
+        for (int v = tid; v < HP * WP * 4; v += 256) {
+          const int pix = v >> 2, part = v & 3;
+          const int py = pix / WP, px = pix - py * WP;
+          const int yy = y0 - 1 + py, xx = x0 - 1 + px;
+          uint4 val = make_uint4(0u, 0u, 0u, 0u);
+          if (yy >= 0 && yy < h && xx >= 0 && xx < w)
+            val = *(const uint4 *)(base + ((long long)yy * w + xx) * cin + ck * CK + part * VEC);
+          *(uint4 *)(&As[pix * ST + part * VEC]) = val;
+        }
+      }
+      {
+        const T *wb = wsrc + ((long long)ck * ntap) * a.cout_pad * CK;
+        const int nvec = ntap * BN * 4;
+        for (int v = tid; v < nvec; v += 256) {
+          const int row = v >> 2, part = v & 3;
+          const int tap = row / BN, n = row - tap * BN;
+          const uint4 val =
+              *(const uint4 *)(wb + ((long long)tap * a.cout_pad + n0 + n) * CK + part * VEC);
+          *(uint4 *)(&Bs[row * ST + part * VEC]) = val;
+        }
+      }
+      __syncthreads();
+
+#pragma unroll 1
+      for (int tap = 0; tap < ntap; ++tap) {
+        int toff;
+        if (seg == 0 && IN == IN_IMAGE) toff = 0;
+        else if (ntap == 9) toff = (tap / 3) * WP + (tap % 3);
+        else toff = WP + 1;
+        typename Mma<T>::Frag af[TM], bfr[TN];
+#pragma unroll
+        for (int tm = 0; tm < TM; ++tm)
+          af[tm] = Mma<T>::load(&As[(pidx[tm] + toff) * ST + half * (CK / 2)]);
+#pragma unroll
+        for (int tn = 0; tn < TN; ++tn) {
+          const int n = wn * TN * 32 + tn * 32 + l32;
+          bfr[tn] = Mma<T>::load(&Bs[(tap * BN + n) * ST + half * (CK / 2)]);
+        }
+#pragma unroll
+        for (int tm = 0; tm < TM; ++tm)
+#pragma unroll
+          for (int tn = 0; tn < TN; ++tn) Mma<T>::mma(acc[tm][tn], af[tm], bfr[tn]);
+      }
+    }
+  }
+
+  // epilogue: D[m][n] of a 32x32 block sits in lane (n, m/4 mod 2) register
+  // 4 (m / 8) + m mod 4.
+  const int cout = a.cout;
+#pragma unroll
+  for (int tm = 0; tm < TM; ++tm)
+#pragma unroll
+    for (int tn = 0; tn < TN; ++tn)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int m = wm * TM * 32 + tm * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+        const int py = y0 + m / PW, px = x0 + m % PW;
+        const int n = n0 + wn * TN * 32 + tn * 32 + l32;
+        if (py >= h || px >= w || n >= cout) continue;
+        const long long pix = (long long)py * w + px;
+        float v = acc[tm][tn][r];
+        if (EPI == EPI_FWD) {
+          v = fmaxf(v + a.bias[n], 0.f);
+          ((T *)a.out)[slot * a.out_ss + pix * cout + n] = from_f<T>(v);
+          if (a.rc) {
+            const float f =
+                a.fc[((long long)(g.gy[t] + py) * a.fc_w + (g.gx[t] + px)) * cout + n];
+            a.rc[slot * a.rc_ss + pix * cout + n] = v - f;
+          }
+        } else if (EPI == EPI_BWD) {
+          if (a.rc) v += a.two_alpha * a.rc[slot * a.rc_ss + pix * cout + n];
+          if (a.mask) {
+            const float mk = to_f(((const T *)a.mask)[slot * a.mask_ss + pix * cout + n]);
+            if (!(mk > 0.f)) v = 0.f;
+          }
+          ((T *)a.out)[slot * a.out_ss + pix * cout + n] = from_f<T>(v);
+        } else {
+          if (py >= g.a0[t] && py < g.a1[t] && px >= g.a2[t] && px < g.a3[t])
+            a.grad[((long long)n * a.img_h + (g.gy[t] + py)) * a.img_w + (g.gx[t] + px)] = v;
+        }
+      }
+}
+
+template <typename T, int PH, int BN, int WM, int WN, int IN, int EPI, bool SEG2>
+static hipError_t run_conv(const ConvArgs &a, const Batch &g, hipStream_t s) {
+  const int nblk = g.pfx[g.n];
+  if (nblk == 0) return hipSuccess;
+  dim3 grid(nblk, (a.cout + BN - 1) / BN);
+  hipLaunchKernelGGL((k_conv<T, PH, BN, WM, WN, IN, EPI, SEG2>), grid, dim3(256), 0, s, a, g);
+  return hipGetLastError();
+}
+
+int conv_block_rows(int precision, int in_mode, int epi, int cout) {
+  (void)precision;
+  (void)in_mode;
+  if (epi == EPI_STITCH) return 8;
+  return cout <= 64 ? 16 : 8;
+}
+int conv_block_px(int precision, int in_mode, int epi, int cout) {
+  return 16 * conv_block_rows(precision, in_mode, epi, cout);
+}
+int ck_of(int precision) { return precision == 1 ? Tr<bf16>::CK : Tr<float>::CK; }
+size_t elem_size(int precision) { return precision == 1 ? 2 : 4; }
+
+template <typename T>
+static hipError_t conv_dispatch(int in_mode, int epi, const ConvArgs &a, const Batch &g,
+                                hipStream_t s) {
+  const bool seg2 = a.in2 != nullptr && a.cin2 > 0;
+  if (epi == EPI_STITCH) {
+    if (in_mode != IN_NHWC || seg2) return hipErrorInvalidValue;
+    return run_conv<T, 8, 32, 4, 1, IN_NHWC, EPI_STITCH, false>(a, g, s);
+  }
+  const bool small = a.cout <= 64;
+  if (epi == EPI_FWD) {
+    if (seg2) return hipErrorInvalidValue;
+    if (in_mode == IN_IMAGE) {
+      if (!small) return hipErrorInvalidValue;
+      return run_conv<T, 16, 64, 4, 1, IN_IMAGE, EPI_FWD, false>(a, g, s);
+    }
+    if (in_mode != IN_NHWC) return hipErrorInvalidValue;
+    if (small) return run_conv<T, 16, 64, 4, 1, IN_NHWC, EPI_FWD, false>(a, g, s);
+    return run_conv<T, 8, 128, 2, 2, IN_NHWC, EPI_FWD, false>(a, g, s);
+  }
+  // EPI_BWD
+  if (in_mode == IN_NHWC) {
+    if (small)
+      return seg2 ? run_conv<T, 16, 64, 4, 1, IN_NHWC, EPI_BWD, true>(a, g, s)
+                  : run_conv<T, 16, 64, 4, 1, IN_NHWC, EPI_BWD, false>(a, g, s);
+    return seg2 ? run_conv<T, 8, 128, 2, 2, IN_NHWC, EPI_BWD, true>(a, g, s)
+                : run_conv<T, 8, 128, 2, 2, IN_NHWC, EPI_BWD, false>(a, g, s);
+  }
+  if (in_mode == IN_NONE) {
+    if (small)
+      return seg2 ? run_conv<T, 16, 64, 4, 1, IN_NONE, EPI_BWD, true>(a, g, s)
+                  : run_conv<T, 16, 64, 4, 1, IN_NONE, EPI_BWD, false>(a, g, s);
+    return seg2 ? run_conv<T, 8, 128, 2, 2, IN_NONE, EPI_BWD, true>(a, g, s)
+                : run_conv<T, 8, 128, 2, 2, IN_NONE, EPI_BWD, false>(a, g, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_conv(int precision, int in_mode, int epi, const ConvArgs &a, const Batch &g,
+                       hipStream_t s) {
+  return precision == 1 ? conv_dispatch<bf16>(in_mode, epi, a, g, s)
+                        : conv_dispatch<float>(in_mode, epi, a, g, s);
+}
+
+// ---------------------------------------------------------------------------------------
+// 16-byte vector helpers (VEC = 16 / sizeof(T) channels)
+// ---------------------------------------------------------------------------------------
+template <typename T> struct Vec {
+  static constexpr int N = 16 / sizeof(T);
+  union {
+    uint4 u;
+    T e[N];
+  };
+};
+
+// 2x2 stride-2 floor-mode max pool, NHWC.  Work item = (output pixel, channel vector).
+template <typename T>
+__global__ __launch_bounds__(256) void k_pool(const T *in, long long in_ss, T *out,
+                                              long long out_ss, int C, Batch g) {
+  const int t = find_tile(g, blockIdx.x);
+  const int item = (blockIdx.x - g.pfx[t]) * 256 + threadIdx.x;
+  const int h = g.h[t], w = g.w[t], ho = h / 2, wo = w / 2;
+  constexpr int N = Vec<T>::N;
+  const int nv = C / N;
+  if (item >= ho * wo * nv) return;
+  const int v = item % nv, p = item / nv, oy = p / wo, ox = p - oy * wo;
+  const T *b = in + g.slot[t] * in_ss;
+  Vec<T> q[4], r;
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    q[k].u = *(const uint4 *)(b + ((long long)(2 * oy + (k >> 1)) * w + 2 * ox + (k & 1)) * C + v * N);
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    float m = to_f(q[0].e[j]);
+    T mv = q[0].e[j];
+#pragma unroll
+    for (int k = 1; k < 4; ++k)
+      if (to_f(q[k].e[j]) > m) {
+        m = to_f(q[k].e[j]);
+        mv = q[k].e[j];
+      }
+    r.e[j] = mv;
+  }
+  *(uint4 *)(out + g.slot[t] * out_ss + ((long long)oy * wo + ox) * C + v * N) = r.u;
+}
+
+// Max-pool backward fused with the content seed and the ReLU mask of the pre-pool layer:
+//   dZ = ([p is the first maximum of its window] dP + 2 alpha rc) * [A > 0]
+// Work item = (pooling window, channel vector); windows cut by floor mode get dP = 0.
+template <typename T>
+__global__ __launch_bounds__(256) void k_pool_bwd(const T *dp, long long dp_ss, const T *act,
+                                                  long long act_ss, const float *rc,
+                                                  long long rc_ss, float two_alpha, T *dz,
+                                                  long long dz_ss, int C, Batch g) {
+  const int t = find_tile(g, blockIdx.x);
+  const int item = (blockIdx.x - g.pfx[t]) * 256 + threadIdx.x;
+  const int h = g.h[t], w = g.w[t];
+  const int hw2 = (h + 1) / 2, ww2 = (w + 1) / 2;
+  constexpr int N = Vec<T>::N;
+  const int nv = C / N;
+  if (item >= hw2 * ww2 * nv) return;
+  const int v = item % nv, p = item / nv, wy = p / ww2, wx = p - wy * ww2;
+  const long long slot = g.slot[t];
+  const bool full = (2 * wy + 1 < h) && (2 * wx + 1 < w);
+  Vec<T> av[4], dv;
+  bool valid[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int yy = 2 * wy + (k >> 1), xx = 2 * wx + (k & 1);
+    valid[k] = yy < h && xx < w;
+    av[k].u = make_uint4(0u, 0u, 0u, 0u);
+    if (valid[k]) av[k].u = *(const uint4 *)(act + slot * act_ss + ((long long)yy * w + xx) * C + v * N);
+  }
+  dv.u = make_uint4(0u, 0u, 0u, 0u);
+  if (full) dv.u = *(const uint4 *)(dp + slot * dp_ss + ((long long)wy * (w / 2) + wx) * C + v * N);
+  int arg[N];
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    float m = to_f(av[0].e[j]);
+    int best = 0;
+#pragma unroll
+    for (int k = 1; k < 4; ++k)
+      if (to_f(av[k].e[j]) > m) {
+        m = to_f(av[k].e[j]);
+        best = k;
+      }
+    arg[j] = full ? best : -1;
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (!valid[k]) continue;
+    const int yy = 2 * wy + (k >> 1), xx = 2 * wx + (k & 1);
+    const long long pix = (long long)yy * w + xx;
+    Vec<T> o;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      float val = (arg[j] == k) ? to_f(dv.e[j]) : 0.f;
+      if (rc) val += two_alpha * rc[slot * rc_ss + pix * C + v * N + j];
+      if (!(to_f(av[k].e[j]) > 0.f)) val = 0.f;
+      o.e[j] = from_f<T>(val);
+    }
+    *(uint4 *)(dz + slot * dz_ss + pix * C + v * N) = o.u;
+  }
+}
+
+hipError_t launch_pool(int precision, const void *in, long long in_ss, void *out,
+                       long long out_ss, int C, const Batch &g, hipStream_t s) {
+  const int nblk = g.pfx[g.n];
+  if (nblk == 0) return hipSuccess;
+  if (precision == 1)
+    hipLaunchKernelGGL(k_pool<bf16>, dim3(nblk), dim3(256), 0, s, (const bf16 *)in, in_ss,
+                       (bf16 *)out, out_ss, C, g);
+  else
+    hipLaunchKernelGGL(k_pool<float>, dim3(nblk), dim3(256), 0, s, (const float *)in, in_ss,
+                       (float *)out, out_ss, C, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_pool_bwd(int precision, const void *dp, long long dp_ss, const void *act,
+                           long long act_ss, const float *rc, long long rc_ss, float two_alpha,
+                           void *dz, long long dz_ss, int C, const Batch &g, hipStream_t s) {
+  const int nblk = g.pfx[g.n];
+  if (nblk == 0) return hipSuccess;
+  if (precision == 1)
+    hipLaunchKernelGGL(k_pool_bwd<bf16>, dim3(nblk), dim3(256), 0, s, (const bf16 *)dp, dp_ss,
+                       (const bf16 *)act, act_ss, rc, rc_ss, two_alpha, (bf16 *)dz, dz_ss, C, g);
+  else
+    hipLaunchKernelGGL(k_pool_bwd<float>, dim3(nblk), dim3(256), 0, s, (const float *)dp, dp_ss,
+                       (const float *)act, act_ss, rc, rc_ss, two_alpha, (float *)dz, dz_ss, C,
+                       g);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------
+// Per-tile Gram partials over owned features (Step 1 of Algorithm 1):
+//   part[slot][chunk] = V_chunk^T V_chunk, chunk = kGramChunk owned pixels in row-major
+//   order over the owned rectangle.  One workgroup = one 64x64 upper-triangle block of
+//   one chunk; wave (wi, wj) computes a 32x32 quadrant with fp32 MFMA 32x32x2, where
+//   lane l supplies channel (i0 or j0) + l mod 32 of pixel q + l / 32: both operands are
+//   plain coalesced NHWC reads.
+// ---------------------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_gram(const T *act, long long act_ss, int C, Batch g,
+                                              float *part, long long part_ss) {
+  const int t = find_tile(g, blockIdx.x);
+  const int k = blockIdx.x - g.pfx[t];
+  const int nb = C / 64;
+  int pair = blockIdx.y, bi = 0;
+  while (pair >= nb - bi) {
+    pair -= nb - bi;
+    ++bi;
+  }
+  const int bj = bi + pair;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int l32 = lane & 31, half = lane >> 5;
+  const int i0 = bi * 64 + (wave >> 1) * 32, j0 = bj * 64 + (wave & 1) * 32;
+  const int w = g.w[t];
+  const int r0 = g.a0[t], r1 = g.a1[t], c0 = g.a2[t], c1 = g.a3[t];
+  const int ow = c1 - c0;
+  const int npx = (r1 - r0) * ow;
+  const int q0 = k * kGramChunk;
+  const int q1 = min(npx, q0 + kGramChunk);
+  const T *b = act + g.slot[t] * act_ss;
+  int qq = q0 + half;
+  int y = r0 + qq / ow, x = c0 + qq % ow;
+  f32x16 acc;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+  for (int q = q0; q < q1; q += 2) {
+    float av = 0.f, bv = 0.f;
+    if (qq < q1) {
+      const long long p = ((long long)y * w + x) * C;
+      av = to_f(b[p + i0 + l32]);
+      bv = to_f(b[p + j0 + l32]);
+    }
+    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
+    qq += 2;
+    x += 2;
+    while (x >= c1) {
+      x -= ow;
+      ++y;
+    }
+  }
+  float *o = part + g.slot[t] * part_ss + (long long)k * C * C;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int i = i0 + 8 * (r >> 2) + 4 * half + (r & 3);
+    o[(long long)i * C + j0 + l32] = acc[r];
+  }
+}
+
+// tilesum[t][i][j] = sum over the tile's chunks (in order) of part[.][k][min(i,j)][max(i,j)]
+__global__ __launch_bounds__(256) void k_gram_tile_reduce(const float *part, long long part_ss,
+                                                          int C, Batch g, double *tilesum) {
+  const int t = blockIdx.y;
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= C * C) return;
+  const int i = e / C, j = e - i * C;
+  const int ii = min(i, j), jj = max(i, j);
+  const int nch = g.pfx[t + 1] - g.pfx[t];
+  const float *p = part + g.slot[t] * part_ss + (long long)ii * C + jj;
+  double s = 0.0;
+  for (int k = 0; k < nch; ++k) s += (double)p[(long long)k * C * C];
+  tilesum[(long long)t * C * C + e] = s;
+}
+
+__global__ __launch_bounds__(256) void k_gram_accum(const double *tilesum, int n_tiles, int CC,
+                                                    double *gacc) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= CC) return;
+  double s = gacc[e];
+  for (int t = 0; t < n_tiles; ++t) s += tilesum[(long long)t * CC + e];
+  gacc[e] = s;
+}
+
+hipError_t launch_gram(int precision, const void *act, long long act_ss, int C, const Batch &g,
+                       float *part, long long part_ss, hipStream_t s) {
+  const int nblk = g.pfx[g.n];
+  if (nblk == 0) return hipSuccess;
+  const int nb = C / 64;
+  dim3 grid(nblk, nb * (nb + 1) / 2);
+  if (precision == 1)
+    hipLaunchKernelGGL(k_gram<bf16>, grid, dim3(256), 0, s, (const bf16 *)act, act_ss, C, g,
+                       part, part_ss);
+  else
+    hipLaunchKernelGGL(k_gram<float>, grid, dim3(256), 0, s, (const float *)act, act_ss, C, g,
+                       part, part_ss);
+  return hipGetLastError();
+}
+
+hipError_t launch_gram_tile_reduce(const float *part, long long part_ss, int C, const Batch &g,
+                                   double *tilesum, hipStream_t s) {
+  if (g.n == 0) return hipSuccess;
+  dim3 grid((C * C + 255) / 256, g.n);
+  hipLaunchKernelGGL(k_gram_tile_reduce, grid, dim3(256), 0, s, part, part_ss, C, g, tilesum);
+  return hipGetLastError();
+}
+
+hipError_t launch_gram_accum(const double *tilesum, int n_tiles, int C, double *gacc,
+                             hipStream_t s) {
+  if (n_tiles == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gram_accum, dim3((C * C + 255) / 256), dim3(256), 0, s, tilesum, n_tiles,
+                     C * C, gacc);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------
+// Content energy partials over owned content features: sum of rc^2 (rc = V - F_c), FP64,
+// fixed-order block reduction; then a single-thread accumulation in (tile, block) order.
+// ---------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_content_partial(const float *rc, long long rc_ss, int C,
+                                                         Batch g, double *part,
+                                                         long long part_ss) {
+  __shared__ double red[256];
+  const int t = find_tile(g, blockIdx.x);
+  const int blk = blockIdx.x - g.pfx[t];
+  const int w = g.w[t];
+  const int r0 = g.a0[t], r1 = g.a1[t], c0 = g.a2[t], c1 = g.a3[t];
+  const int ow = c1 - c0, npx = (r1 - r0) * ow;
+  const float *b = rc + g.slot[t] * rc_ss;
+  double s = 0.0;
+  for (int e = threadIdx.x; e < kContentBlockPx * C; e += 256) {
+    const int pl = e / C, c = e - pl * C;
+    const int q = blk * kContentBlockPx + pl;
+    if (q < npx) {
+      const int y = r0 + q / ow, x = c0 + q % ow;
+      const double d = b[((long long)y * w + x) * C + c];
+      s += d * d;
+    }
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[g.slot[t] * part_ss + blk] = red[0];
+}
+
+__global__ void k_content_accum(const double *part, long long part_ss, Batch g, double *acc) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double s = acc[0];
+  for (int t = 0; t < g.n; ++t) {
+    const int nb = g.pfx[t + 1] - g.pfx[t];
+    for (int b = 0; b < nb; ++b) s += part[g.slot[t] * part_ss + b];
+  }
+  acc[0] = s;
+}
+
+hipError_t launch_content_partial(const float *rc, long long rc_ss, int C, const Batch &g,
+                                  double *part, long long part_ss, hipStream_t s) {
+  const int nblk = g.pfx[g.n];
+  if (nblk == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_content_partial, dim3(nblk), dim3(256), 0, s, rc, rc_ss, C, g, part,
+                     part_ss);
+  return hipGetLastError();
+}
+
+hipError_t launch_content_accum(const double *part, long long part_ss, const Batch &g,
+                                double *acc, hipStream_t s) {
+  hipLaunchKernelGGL(k_content_accum, dim3(1), dim3(64), 0, s, part, part_ss, g, acc);
+  return hipGetLastError();
+}
+
+// Owned features of a layer -> whole-image fp32 map (h x w x C).
+template <typename T>
+__global__ __launch_bounds__(256) void k_stitch_feats(const T *act, long long act_ss, int C,
+                                                      Batch g, float *feats, int fw) {
+  const int t = find_tile(g, blockIdx.x);
+  const int item = (blockIdx.x - g.pfx[t]) * 256 + threadIdx.x;
+  constexpr int N = Vec<T>::N;
+  const int nv = C / N;
+  const int r0 = g.a0[t], r1 = g.a1[t], c0 = g.a2[t], c1 = g.a3[t];
+  const int ow = c1 - c0;
+  if (item >= (r1 - r0) * ow * nv) return;
+  const int v = item % nv, p = item / nv;
+  const int y = r0 + p / ow, x = c0 + p % ow;
+  Vec<T> q;
+  q.u = *(const uint4 *)(act + g.slot[t] * act_ss + ((long long)y * g.w[t] + x) * C + v * N);
+  float *o = feats + ((long long)(g.gy[t] + y) * fw + (g.gx[t] + x)) * C + v * N;
+#pragma unroll
+  for (int j = 0; j < N; ++j) o[j] = to_f(q.e[j]);
+}
+
+hipError_t launch_stitch_feats(int precision, const void *act, long long act_ss, int C,
+                               const Batch &g, float *feats, int feats_w, hipStream_t s) {
+  const int nblk = g.pfx[g.n];
+  if (nblk == 0) return hipSuccess;
+  if (precision == 1)
+    hipLaunchKernelGGL(k_stitch_feats<bf16>, dim3(nblk), dim3(256), 0, s, (const bf16 *)act,
+                       act_ss, C, g, feats, feats_w);
+  else
+    hipLaunchKernelGGL(k_stitch_feats<float>, dim3(nblk), dim3(256), 0, s, (const float *)act,
+                       act_ss, C, g, feats, feats_w);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------
+// Small utility kernels
+// ---------------------------------------------------------------------------------------
+__global__ void k_fill_f64(double *p, size_t n, double v) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+__global__ void k_fill_f32(float *p, size_t n, float v) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+hipError_t launch_fill_f64(double *p, size_t n, double v, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_f64, dim3((n + 255) / 256), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+hipError_t launch_fill_f32(float *p, size_t n, float v, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_f32, dim3((n + 255) / 256), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+__global__ void k_div_f64(const double *in, double *out, size_t n, double d) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) out[i] = in[i] / d;
+}
+hipError_t launch_gram_normalize(const double *gacc, double *g, size_t n, double n_p,
+                                 hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_div_f64, dim3((n + 255) / 256), dim3(256), 0, s, gacc, g, n, n_p);
+  return hipGetLastError();
+}
+
+// Style energy terms and the packed residual operand, one workgroup per style layer.
+//   e_style[l] = w_l sum_ij (G - Ghat)_ij^2                      (Eq. 3)
+//   B[k = i][n = j] = (2 w_l / n_p) (D_ij + D_ji), D = G - Ghat   (Table 1, Gram row)
+// packed as [i / CK][j][i mod CK] in compute precision.
+template <typename T>
+__global__ __launch_bounds__(256) void k_style_terms(const double *g, const double *gt,
+                                                     StyleTermsArgs a, T *dt, double *e_style) {
+  __shared__ double red[256];
+  const int l = blockIdx.x;
+  const int C = a.C[l];
+  constexpr int CK = Tr<T>::CK;
+  const double *G = g + a.off[l], *H = gt + a.off[l];
+  T *D = dt + a.dt_off[l];
+  const double coef = 2.0 * a.w[l] * a.inv_np[l];
+  double s = 0.0;
+  for (int e = threadIdx.x; e < C * C; e += 256) {
+    const int i = e / C, j = e - i * C;
+    const double dij = G[e] - H[e];
+    const double dji = G[(long long)j * C + i] - H[(long long)j * C + i];
+    s += dij * dij;
+    D[((long long)(i / CK) * C + j) * CK + (i % CK)] = from_f<T>((float)(coef * (dij + dji)));
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) e_style[l] = a.w[l] * red[0];
+}
+
+hipError_t launch_style_terms(int precision, const double *g, const double *gt,
+                              const StyleTermsArgs &a, void *dt, double *e_style, hipStream_t s) {
+  if (a.n_style == 0) return hipSuccess;
+  if (precision == 1)
+    hipLaunchKernelGGL(k_style_terms<bf16>, dim3(a.n_style), dim3(256), 0, s, g, gt, a,
+                       (bf16 *)dt, e_style);
+  else
+    hipLaunchKernelGGL(k_style_terms<float>, dim3(a.n_style), dim3(256), 0, s, g, gt, a,
+                       (float *)dt, e_style);
+  return hipGetLastError();
+}
+
+__global__ void k_energy_total(const double *ec, const double *e_style, int n_style,
+                               double alpha, double *energy) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double c = alpha * ec[0];
+  double e = c;
+  for (int l = 0; l < n_style; ++l) {
+    energy[2 + l] = e_style[l];
+    e += e_style[l];
+  }
+  energy[0] = e;
+  energy[1] = c;
+}
+
+hipError_t launch_energy_total(const double *ec, const double *e_style, int n_style,
+                               double alpha, double *energy, hipStream_t s) {
+  hipLaunchKernelGGL(k_energy_total, dim3(1), dim3(64), 0, s, ec, e_style, n_style, alpha,
+                     energy);
+  return hipGetLastError();
+}
+
+}  // namespace nst
