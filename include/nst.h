@@ -69,8 +69,9 @@ enum {
 /* A VGG-style feature network: n_conv 3x3 convs (zero padding 1, stride 1), each followed
  * by ReLU, some followed by a 2x2 stride-2 floor-mode max pool.  Style layers and the
  * content layer name convs whose post-ReLU (pre-pool) output is used.  Supported shapes:
- * c_in[0] == 3; c_in[i] == c_out[i-1]; c_out[i] a multiple of 32; a style layer is not
- * followed by a pool unless it is the last conv; the last conv is a style or content layer. */
+ * c_in[0] == 3; c_in[i] == c_out[i-1]; c_out[i] == 64 or a multiple of 128; no style layer
+ * is followed by a pool below the deepest used conv; convs after the deepest style/content
+ * layer are ignored. */
 typedef struct {
   int n_conv;
   int c_in[NST_MAX_CONV];
@@ -121,9 +122,9 @@ int nst_create(const nst_net_desc *net, const float *const *w, const float *cons
                int precision, nst_ctx **out);
 void nst_destroy(nst_ctx *ctx);
 
-/* Global style Grams of image s (3 x H x W), computed block by block (Algorithm 1 Require:
- * statistics of the style image "computed block by block").  grams: device float64 output,
- * sum_l C_l^2 values. */
+/* Global style Grams of image s (3 x H x W), accumulated tile by tile like Step 1 of
+ * Algorithm 1 (its Require line takes the style statistics from such a pass).  grams: device
+ * float64 output, sum_l C_l^2 values. */
 int nst_style_grams(nst_ctx *ctx, const float *s, int H, int W, int T, int m, double *grams,
                     void *ws, size_t ws_bytes, void *stream);
 
@@ -154,6 +155,28 @@ int nst_loss_grad(nst_ctx *ctx, const float *x, int H, int W, const double *targ
                   const float *content_feats, const double *w_style, double alpha, int T,
                   int m, int flags, double *grams_x, double *energy, float *grad, void *ws,
                   size_t ws_bytes, void *stream);
+
+/* ---- Profiling (instrumentation of the entry points above; not part of the method) ----
+ * While enabled, every kernel the run calls enqueue is bracketed by two HIP events on the
+ * caller's stream.  nst_profile_read() waits for those events and returns, per kernel
+ * instantiation (its demangled name, as profilers list it), the launch count, the summed
+ * event time, and the summed algorithmic work of those launches: FLOPs = 2 x (output
+ * pixels) x (output channels) x (multiply-adds per output) with no padding counted, and
+ * bytes = minimal HBM traffic (each operand read once, each result written once).
+ * Recording adds ~2 event records per launch; it neither reorders nor synchronizes work. */
+typedef struct {
+  char name[160];
+  int launches;
+  double ms;
+  double flops;
+  double bytes;
+} nst_kstat;
+
+/* enable != 0: clear previous records and start recording; enable == 0: stop. */
+int nst_profile(nst_ctx *ctx, int enable);
+/* Aggregate the records (synchronizing on their events), write min(cap, count) entries
+ * sorted by decreasing time, set *n to the count, and clear the records. */
+int nst_profile_read(nst_ctx *ctx, nst_kstat *out, int cap, int *n);
 
 #ifdef __cplusplus
 }

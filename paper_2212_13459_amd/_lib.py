@@ -29,6 +29,11 @@ class Tile(ctypes.Structure):
                 ("own", (c_int * 4) * NST_MAX_CONV)]
 
 
+class KStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 160), ("launches", c_int), ("ms", c_double), ("flops", c_double),
+                ("bytes", c_double)]
+
+
 class NstError(RuntimeError):
     def __init__(self, fn, status, lib=None):
         msg = STATUS.get(status, str(status))
@@ -56,6 +61,8 @@ SIGNATURES = {
                                 c_size_t, c_void_p]),
     "nst_content_feats": (c_int, [c_void_p, c_void_p, c_int, c_int, c_int, c_int, c_void_p, c_void_p, c_size_t,
                                   c_void_p]),
+    "nst_profile": (c_int, [c_void_p, c_int]),
+    "nst_profile_read": (c_int, [c_void_p, POINTER(KStat), c_int, POINTER(c_int)]),
     "nst_loss_grad": (c_int, [c_void_p, c_void_p, c_int, c_int, c_void_p, c_void_p, POINTER(c_double), c_double,
                               c_int, c_int, c_int, c_void_p, POINTER(c_double), c_void_p, c_void_p, c_size_t,
                               c_void_p]),

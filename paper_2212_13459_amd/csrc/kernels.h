@@ -65,6 +65,8 @@ size_t elem_size(int precision);
 hipError_t launch_conv(int precision, int in_mode, int epi, const ConvArgs &a, const Batch &g,
                        hipStream_t s);
 int conv_block_px(int precision, int in_mode, int epi, int cout);   // pixels per work block
+// Demangled name of the kernel instantiation launch_conv would pick (as profilers list it).
+const char *conv_kernel_name(int precision, int in_mode, int epi, const ConvArgs &a);
 int conv_block_rows(int precision, int in_mode, int epi, int cout); // patch rows (cols fixed at 16)
 
 hipError_t launch_pool(int precision, const void *in, long long in_ss, void *out,

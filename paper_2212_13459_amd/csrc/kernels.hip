@@ -11,6 +11,7 @@
 // size.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <stdio.h>
 
 #include "kernels.h"
 
@@ -290,6 +291,24 @@ static hipError_t conv_dispatch(int in_mode, int epi, const ConvArgs &a, const B
                 : run_conv<T, 8, 128, 2, 2, IN_NONE, EPI_BWD, false>(a, g, s);
   }
   return hipErrorInvalidValue;
+}
+
+const char *conv_kernel_name(int precision, int in_mode, int epi, const ConvArgs &a) {
+  static char buf[8][160];
+  static int k = 0;
+  char *o = buf[k++ & 7];
+  const bool seg2 = a.in2 != nullptr && a.cin2 > 0;
+  int ph, bn, wm, wn;
+  if (epi == EPI_STITCH) {
+    ph = 8; bn = 32; wm = 4; wn = 1;
+  } else if (a.cout <= 64) {
+    ph = 16; bn = 64; wm = 4; wn = 1;
+  } else {
+    ph = 8; bn = 128; wm = 2; wn = 2;
+  }
+  snprintf(o, 160, "void nst::k_conv<%s, %d, %d, %d, %d, %d, %d, %s>(nst::ConvArgs, nst::Batch)",
+           precision == 1 ? "__bf16" : "float", ph, bn, wm, wn, in_mode, epi, seg2 ? "true" : "false");
+  return o;
 }
 
 hipError_t launch_conv(int precision, int in_mode, int epi, const ConvArgs &a, const Batch &g,

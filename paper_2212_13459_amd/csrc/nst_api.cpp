@@ -5,8 +5,11 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <cstdio>
 #include <cstring>
+#include <map>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "../../include/nst.h"
@@ -263,8 +266,17 @@ uint16_t f2bf(float f) {
 
 // ---------------------------------------------------------------------- ctx ----------
 
+struct ProfRec {
+  std::string name;
+  double flops, bytes;
+  hipEvent_t e0, e1;
+};
+
 struct nst_ctx {
   Geom g;
+  bool prof_on = false;
+  std::vector<ProfRec> prof;
+  std::vector<hipEvent_t> ev_pool;
   int prec = 0;
   int device = 0;
   void *wf[NST_MAX_CONV] = {};   // forward B operand
@@ -461,6 +473,11 @@ int nst_create(const nst_net_desc *net, const float *const *w, const float *cons
 
 void nst_destroy(nst_ctx *c) {
   if (!c) return;
+  for (ProfRec &r : c->prof) {
+    (void)hipEventDestroy(r.e0);
+    (void)hipEventDestroy(r.e1);
+  }
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   for (int i = 0; i < NST_MAX_CONV; ++i) {
     if (c->wf[i]) (void)hipFree(c->wf[i]);
     if (c->wd[i]) (void)hipFree(c->wd[i]);
@@ -490,6 +507,50 @@ struct Runner {
   int H, W;
 
   Runner(nst_ctx *ctx) : c(ctx), g(ctx->g) {}
+
+  hipEvent_t get_event() {
+    if (!c->ev_pool.empty()) {
+      hipEvent_t e = c->ev_pool.back();
+      c->ev_pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  // Enqueue `launch` bracketed by events when profiling is on.
+  template <typename F>
+  hipError_t prof(const char *name, double flops, double bytes, F &&launch) {
+    if (!c->prof_on) return launch();
+    ProfRec r{name, flops, bytes, get_event(), get_event()};
+    if (!r.e0 || !r.e1) return hipErrorOutOfMemory;
+    hipError_t e = hipEventRecord(r.e0, s);
+    if (e != hipSuccess) return e;
+    e = launch();
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(r.e1, s);
+    c->prof.push_back(r);
+    return e;
+  }
+  hipError_t conv(int in_mode, int epi, const ConvArgs &a, const Batch &b) {
+    double px = 0;
+    for (int k = 0; k < b.n; ++k) px += (double)b.h[k] * b.w[k];
+    const double es = (double)L.es;
+    double mac, in_b;
+    if (in_mode == IN_IMAGE) {
+      mac = 27.0;
+      in_b = 12.0;
+    } else {
+      mac = (in_mode == IN_NHWC ? 9.0 * a.cin : 0.0) + (a.in2 ? (double)a.cin2 : 0.0);
+      in_b = ((in_mode == IN_NHWC ? a.cin : 0) + (a.in2 ? a.cin2 : 0)) * es;
+    }
+    const double cout = epi == EPI_STITCH ? 3.0 : (double)a.cout;
+    double out_b = epi == EPI_STITCH ? 12.0 : cout * es;
+    if (a.mask) out_b += cout * es;
+    if (a.rc) out_b += cout * 4.0;
+    return prof(conv_kernel_name(c->prec, in_mode, epi, a), 2.0 * px * cout * mac,
+                px * (in_b + out_b), [&] { return launch_conv(c->prec, in_mode, epi, a, b, s); });
+  }
 
   template <typename T> T *gl(size_t off) const { return (T *)(ws + off); }
   char *slot_base(size_t off) const { return ws + L.slots + off; }
@@ -569,14 +630,20 @@ struct Runner {
         a.fc_w = W / g.stride[i];
       }
       conv_pfx(b, in_mode, EPI_FWD, a.cout);
-      HIPCHK(launch_conv(c->prec, in_mode, EPI_FWD, a, b, s));
+      HIPCHK(conv(in_mode, EPI_FWD, a, b));
       if (g.pool[i] && i < upto) {
         std::vector<long long> items(n);
         for (int k = 0; k < n; ++k)
           items[k] = (long long)(b.h[k] / 2) * (b.w[k] / 2) * (g.cout[i] / vec);
         items_pfx(b, items, 256);
-        HIPCHK(launch_pool(c->prec, slot_base(L.s_act[i]), ss(es), slot_base(L.s_pool[i]),
-                           ss(es), g.cout[i], b, s));
+        double px = 0;
+        for (int k = 0; k < n; ++k) px += (double)b.h[k] * b.w[k];
+        HIPCHK(prof(c->prec == 1 ? "void nst::k_pool<__bf16>(__bf16 const*, long long, __bf16*, long long, int, nst::Batch)"
+                                 : "void nst::k_pool<float>(float const*, long long, float*, long long, int, nst::Batch)",
+                    0.0, 1.25 * px * g.cout[i] * es, [&] {
+                      return launch_pool(c->prec, slot_base(L.s_act[i]), ss(es), slot_base(L.s_pool[i]),
+                                         ss(es), g.cout[i], b, s);
+                    }));
       }
     }
     return NST_OK;
@@ -590,7 +657,13 @@ struct Runner {
       for (int t = 0; t < n; ++t) items[t] = region_px(b, t);
       items_pfx(b, items, kGramChunk);
       float *part = (float *)slot_base(L.s_gpart[k]);
-      HIPCHK(launch_gram(c->prec, slot_base(L.s_act[i]), ss(L.es), C, b, part, ss(4), s));
+      double npx = 0;
+      for (int t = 0; t < n; ++t) npx += (double)items[t];
+      HIPCHK(prof(c->prec == 1 ? "void nst::k_gram<__bf16>(__bf16 const*, long long, int, nst::Batch, float*, long long)"
+                               : "void nst::k_gram<float>(float const*, long long, int, nst::Batch, float*, long long)",
+                  2.0 * npx * C * C, npx * C * L.es, [&] {
+                    return launch_gram(c->prec, slot_base(L.s_act[i]), ss(L.es), C, b, part, ss(4), s);
+                  }));
       HIPCHK(launch_gram_tile_reduce(part, ss(4), C, b, gl<double>(L.g_tilesum), s));
       HIPCHK(launch_gram_accum(gl<double>(L.g_tilesum), n, C,
                                gl<double>(L.g_gacc) + L.off_c[k], s));
@@ -642,7 +715,7 @@ struct Runner {
       a.cout = g.cout[top];
       a.cout_pad = g.cout[top];
       conv_pfx(b, IN_NONE, EPI_BWD, a.cout);
-      HIPCHK(launch_conv(c->prec, IN_NONE, EPI_BWD, a, b, s));
+      HIPCHK(conv(IN_NONE, EPI_BWD, a, b));
     }
     for (int i = top; i >= 1; --i) {
       Batch b = base_batch(first, n, i);
@@ -658,7 +731,7 @@ struct Runner {
       a.out_ss = ss(es);
       if (!g.pool[i - 1]) fill_seeds(a, i - 1);
       conv_pfx(b, IN_NHWC, EPI_BWD, a.cout);
-      HIPCHK(launch_conv(c->prec, IN_NHWC, EPI_BWD, a, b, s));
+      HIPCHK(conv(IN_NHWC, EPI_BWD, a, b));
       if (g.pool[i - 1]) {
         // oth holds dE/d(pool output); route it back and apply seeds + mask
         Batch bp = base_batch(first, n, i - 1);
@@ -668,9 +741,15 @@ struct Runner {
           items[t] = (long long)((bp.h[t] + 1) / 2) * ((bp.w[t] + 1) / 2) * (C / vec);
         items_pfx(bp, items, 256);
         const bool cont = (i - 1) == g.content && use_content;
-        HIPCHK(launch_pool_bwd(c->prec, oth, ss(es), slot_base(L.s_act[i - 1]), ss(es),
-                               cont ? (const float *)slot_base(L.s_rc) : nullptr, ss(4),
-                               two_alpha, cur, ss(es), C, bp, s));
+        double px = 0;
+        for (int t = 0; t < n; ++t) px += (double)bp.h[t] * bp.w[t];
+        HIPCHK(prof(c->prec == 1 ? "void nst::k_pool_bwd<__bf16>(__bf16 const*, long long, __bf16 const*, long long, float const*, long long, float, __bf16*, long long, int, nst::Batch)"
+                                 : "void nst::k_pool_bwd<float>(float const*, long long, float const*, long long, float const*, long long, float, float*, long long, int, nst::Batch)",
+                    0.0, 2.25 * px * C * es + (cont ? 4.0 * px * C : 0.0), [&] {
+                      return launch_pool_bwd(c->prec, oth, ss(es), slot_base(L.s_act[i - 1]), ss(es),
+                                             cont ? (const float *)slot_base(L.s_rc) : nullptr, ss(4),
+                                             two_alpha, cur, ss(es), C, bp, s);
+                    }));
       } else {
         std::swap(cur, oth);
       }
@@ -696,7 +775,7 @@ struct Runner {
       a.img_h = H;
       a.img_w = W;
       conv_pfx(b, IN_NHWC, EPI_STITCH, 32);
-      HIPCHK(launch_conv(c->prec, IN_NHWC, EPI_STITCH, a, b, s));
+      HIPCHK(conv(IN_NHWC, EPI_STITCH, a, b));
     }
     return NST_OK;
   }
@@ -766,6 +845,48 @@ int normalize(Runner &R, double *grams_out) {
 }  // namespace
 
 extern "C" {
+
+int nst_profile(nst_ctx *ctx, int enable) {
+  if (!ctx) return NST_EINVAL;
+  if (enable) {
+    for (ProfRec &r : ctx->prof) {
+      ctx->ev_pool.push_back(r.e0);
+      ctx->ev_pool.push_back(r.e1);
+    }
+    ctx->prof.clear();
+  }
+  ctx->prof_on = enable != 0;
+  return NST_OK;
+}
+
+int nst_profile_read(nst_ctx *ctx, nst_kstat *out, int cap, int *n) {
+  if (!ctx || !n || cap < 0 || (cap > 0 && !out)) return NST_EINVAL;
+  std::map<std::string, nst_kstat> agg;
+  int st = NST_OK;
+  for (ProfRec &r : ctx->prof) {
+    float ms = 0.f;
+    if (hipEventSynchronize(r.e1) != hipSuccess || hipEventElapsedTime(&ms, r.e0, r.e1) != hipSuccess)
+      st = NST_EHIP;
+    nst_kstat &k = agg[r.name];
+    k.launches += 1;
+    k.ms += ms;
+    k.flops += r.flops;
+    k.bytes += r.bytes;
+    ctx->ev_pool.push_back(r.e0);
+    ctx->ev_pool.push_back(r.e1);
+  }
+  ctx->prof.clear();
+  std::vector<nst_kstat> v;
+  for (auto &kv : agg) {
+    nst_kstat k = kv.second;
+    std::snprintf(k.name, sizeof(k.name), "%s", kv.first.c_str());
+    v.push_back(k);
+  }
+  std::sort(v.begin(), v.end(), [](const nst_kstat &a, const nst_kstat &b) { return a.ms > b.ms; });
+  *n = (int)v.size();
+  for (int i = 0; i < std::min(cap, (int)v.size()); ++i) out[i] = v[i];
+  return st;
+}
 
 int nst_style_grams(nst_ctx *ctx, const float *s, int H, int W, int T, int m, double *grams,
                     void *ws, size_t ws_bytes, void *stream) {

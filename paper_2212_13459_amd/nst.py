@@ -107,6 +107,19 @@ class Context:
         except Exception:
             pass
 
+    # ------------------------------------------------------------- profiling
+    def profile(self, enable: bool):
+        check("nst_profile", lib().nst_profile(self._h, int(enable)))
+
+    def profile_read(self):
+        """Per-kernel [name, launches, ms, flops, bytes], longest total time first."""
+        from ._lib import KStat
+        n = c_int(0)
+        arr = (KStat * 256)()
+        check("nst_profile_read", lib().nst_profile_read(self._h, arr, 256, byref(n)))
+        return [dict(name=k.name.decode(), launches=k.launches, ms=k.ms, flops=k.flops, bytes=k.bytes)
+                for k in arr[: min(n.value, 256)]]
+
     # --------------------------------------------------------------- helpers
     def gram_sizes(self):
         return [self.convs[i][1] for i in self.style]
