@@ -77,25 +77,33 @@ def content_seed(v: np.ndarray, f_ref: np.ndarray, alpha: float) -> np.ndarray:
     return 2.0 * alpha * (v - f_ref)
 
 
-def backward(net: NetSpec, acts, seeds: dict, ws) -> np.ndarray:
-    """Reverse pass: seeds[i] is dE/dA_i added at conv i's ReLU output; returns dE/dx."""
+def backward(net: NetSpec, acts, seeds: dict, ws, record: dict | None = None) -> np.ndarray:
+    """Reverse pass: seeds[i] is dE/dA_i added at conv i's ReLU output; returns dE/dx.
+    With ``record``, stores dE/dA_i (seeds included) under ("dA", i) and the gradient
+    reaching a pool's output under ("dP", i) for the pool after conv i."""
     top = len(acts) - 1
     g = None
     for i in range(top, -1, -1):
         da = np.zeros_like(acts[i]) if g is None else g
         if i in seeds:
             da = da + seeds[i]
+        if record is not None:
+            record[("dA", i)] = da
         dz = np.where(acts[i] > 0.0, da, 0.0)          # ReLU'(0) = 0
         dx = conv3x3_adjoint(dz, ws[i])
         if i > 0 and (i - 1) in net.pool_after:
+            if record is not None:
+                record[("dP", i - 1)] = dx
             g = maxpool2_backward(dx, acts[i - 1])
         else:
             g = dx
     return g
 
 
-def loss_grad(net: NetSpec, x, ws, bs, grams_t, f_c, w_style, alpha, want_grad=True):
-    """Whole-image E (with terms), Grams of x and dE/dx (Eq. 1-3, Table 1)."""
+def loss_grad(net: NetSpec, x, ws, bs, grams_t, f_c, w_style, alpha, want_grad=True, record=None):
+    """Whole-image E (with terms), Grams of x and dE/dx (Eq. 1-3, Table 1).
+    ``record`` (a dict) receives the activations under ("A", i) and the adjoints of
+    ``backward``."""
     acts = forward(net, x, ws, bs)
     grams_x, n_ps = [], []
     for i in net.style:
@@ -115,4 +123,7 @@ def loss_grad(net: NetSpec, x, ws, bs, grams_t, f_c, w_style, alpha, want_grad=T
     if net.content is not None and alpha != 0.0:
         cs = content_seed(acts[net.content], f_c, alpha)
         seeds[net.content] = seeds.get(net.content, 0.0) + cs
-    return terms, backward(net, acts, seeds, ws)
+    if record is not None:
+        for i, a in enumerate(acts):
+            record[("A", i)] = a
+    return terms, backward(net, acts, seeds, ws, record)

@@ -81,13 +81,18 @@ def tiled_content_features(net: NetSpec, c_img, ws, bs, t, m):
     return out
 
 
-def step2(net: NetSpec, x, ws, grams_x, grams_t, f_c, w_style, alpha, t, m, bs):
+def step2(net: NetSpec, x, ws, grams_x, grams_t, f_c, w_style, alpha, t, m, bs, only=None):
+    """Step 2 of Algorithm 1.  ``only``: indices of the plan's tiles to process (the
+    gradient elsewhere is left at zero)."""
     h, w = x.shape[1:]
     strides = net.strides()
     grad = np.zeros((3, h, w))
     n_ps = [(h // strides[i]) * (w // strides[i]) for i in net.style]
     use_c = net.content is not None and alpha != 0.0
-    for tile in _plan(net, h, w, t, m):
+    plan = _plan(net, h, w, t, m)
+    for ti, tile in enumerate(plan):
+        if only is not None and ti not in only:
+            continue
         acts = forward(net, x[:, tile.ey0:tile.ey1, tile.ex0:tile.ex1], ws, bs, upto=last_needed(net))
         seeds = {}
         for k, i in enumerate(net.style):

@@ -235,6 +235,204 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a, Batch g) {
       }
 }
 
+// ---------------------------------------------------------------------------------------
+// Pipelined implicit-GEMM 3x3 convolution (NHWC input) on MFMA.
+//   Work block: a 16 x 16 output patch (M = 256 pixels) x BN output channels, 4 waves in a
+//   WM x WN grid.  The K loop runs over stages (channel chunk c, filter row ky): each stage
+//   stages the 3 taps of one filter row for BN channels in LDS, and the first stage of a
+//   chunk also stages the 18 x 18 halo patch of that chunk.  Stages are double-buffered:
+//   the global loads of stage s+1 are in flight (in registers) while the MFMAs of stage s
+//   run, then land in the other LDS buffer; one barrier per stage.
+//   LDS rows are 64 bytes (four 16-byte chunks) with the chunk index XOR-swizzled by
+//   (row / 2) mod 4, so the 8 lanes of each ds_read_b128 phase hit distinct banks.
+//   Segment 1 (optional) adds the centre tap over in2 (the style residual V D~).
+// ---------------------------------------------------------------------------------------
+template <typename T, int BN, int WM, int WN, int EPI, bool SEG2>
+__global__ __launch_bounds__(256) void k_conv2(ConvArgs a, Batch g) {
+  constexpr int PH = 16, PW = 16, BM = PH * PW;
+  constexpr int TM = BM / (WM * 32), TN = BN / (WN * 32);
+  static_assert(WM * WN == 4 && TM >= 1 && TN >= 1, "bad wave tiling");
+  constexpr int CK = Tr<T>::CK;
+  constexpr int VEC = 16 / sizeof(T);
+  constexpr int HP = PH + 2, WP = PW + 2;
+  constexpr int AROWS = HP * WP;
+  constexpr int BROWS = 3 * BN;
+  constexpr int ANV = (AROWS * 4 + 255) / 256;
+  constexpr int BNV = (BROWS * 4 + 255) / 256;
+  __shared__ __attribute__((aligned(16))) T As[2][AROWS * CK];
+  __shared__ __attribute__((aligned(16))) T Bs[2][BROWS * CK];
+
+  const int t = find_tile(g, blockIdx.x);
+  const int lb = blockIdx.x - g.pfx[t];
+  const int h = g.h[t], w = g.w[t];
+  const int nbx = (w + PW - 1) / PW;
+  const int y0 = (lb / nbx) * PH, x0 = (lb % nbx) * PW;
+  const int n0 = blockIdx.y * BN;
+  const long long slot = g.slot[t];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  const int l32 = lane & 31, half = lane >> 5;
+
+  auto swz = [](int row, int chunk) { return row * CK + ((chunk ^ ((row >> 1) & 3)) * VEC); };
+
+  int pidx[TM];
+#pragma unroll
+  for (int tm = 0; tm < TM; ++tm) {
+    const int m = wm * TM * 32 + tm * 32 + l32;
+    pidx[tm] = (m / PW) * WP + (m % PW);
+  }
+
+  f32x16 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+  const int n0s = (a.cin / CK) * 3;
+  const int ns = n0s + (SEG2 ? a.cin2 / CK : 0);
+  uint4 ra[ANV], rb[BNV];
+
+  // Iteration st: issue the global loads of stage st+1 into registers, run the MFMAs of
+  // stage st from LDS, then write the registers to the other LDS buffers.
+#pragma unroll 1
+  for (int st = -1; st < ns; ++st) {
+    const int nx = st + 1;
+    // decode stage nx: segment, chunk, filter row, A-buffer counter
+    const bool nseg1 = nx >= n0s;
+    const int nc = nseg1 ? nx - n0s : nx / 3;
+    const int nky = nseg1 ? 1 : nx - 3 * nc;
+    const int nac = nseg1 ? n0s / 3 + nc : nc;
+    const bool nnewA = nseg1 || nky == 0;
+    const int nrows = nseg1 ? BN : BROWS;
+    if (nx < ns) {
+      if (nnewA) {
+        const T *src = (const T *)(nseg1 ? a.in2 : a.in) + slot * (nseg1 ? a.in2_ss : a.in_ss);
+        const int cin = nseg1 ? a.cin2 : a.cin;
+#pragma unroll
+        for (int i = 0; i < ANV; ++i) {
+          const int v = tid + i * 256;
+          const int pix = v >> 2, part = v & 3;
+          const int py = pix / WP, px = pix - py * WP;
+          const int yy = y0 - 1 + py, xx = x0 - 1 + px;
+          const bool ok = v < AROWS * 4 && yy >= 0 && yy < h && xx >= 0 && xx < w;
+          const T *p = src + ((long long)(ok ? yy : 0) * w + (ok ? xx : 0)) * cin + nc * CK + part * VEC;
+          ra[i] = ok ? *(const uint4 *)p : make_uint4(0u, 0u, 0u, 0u);
+        }
+      }
+      const T *wb = (const T *)(nseg1 ? a.wp2 : a.wp) +
+                    ((long long)nc * (nseg1 ? 1 : 9) + (nseg1 ? 0 : nky * 3)) * a.cout_pad * CK;
+#pragma unroll
+      for (int i = 0; i < BNV; ++i) {
+        const int v = tid + i * 256;
+        const int row = v >> 2, part = v & 3;
+        const int ti = row / BN, n = row - ti * BN;
+        const bool ok = v < nrows * 4;
+        const T *p = wb + ((long long)(ok ? ti : 0) * a.cout_pad + n0 + (ok ? n : 0)) * CK + part * VEC;
+        rb[i] = ok ? *(const uint4 *)p : make_uint4(0u, 0u, 0u, 0u);
+      }
+    }
+    if (st >= 0) {
+      const bool seg1 = st >= n0s;
+      const int c = seg1 ? st - n0s : st / 3;
+      const int ky = seg1 ? 1 : st - 3 * c;
+      const int ac = seg1 ? n0s / 3 + c : c;
+      const T *A = As[ac & 1];
+      const T *B = Bs[st & 1];
+      const int ntap = seg1 ? 1 : 3;
+#pragma unroll 1
+      for (int ti = 0; ti < ntap; ++ti) {
+        const int toff = seg1 ? WP + 1 : ky * WP + ti;
+        typename Mma<T>::Frag af[TM], bfr[TN];
+#pragma unroll
+        for (int tm = 0; tm < TM; ++tm) {
+          const int row = pidx[tm] + toff;
+          if constexpr (sizeof(T) == 2) {
+            af[tm].v[0] = *(const bf16x8 *)(&A[swz(row, 2 * half)]);
+            af[tm].v[1] = *(const bf16x8 *)(&A[swz(row, 2 * half + 1)]);
+          } else {
+            af[tm].v[0] = *(const f32x4 *)(&A[swz(row, 2 * half)]);
+            af[tm].v[1] = *(const f32x4 *)(&A[swz(row, 2 * half + 1)]);
+          }
+        }
+#pragma unroll
+        for (int tn = 0; tn < TN; ++tn) {
+          const int row = ti * BN + wn * TN * 32 + tn * 32 + l32;
+          if constexpr (sizeof(T) == 2) {
+            bfr[tn].v[0] = *(const bf16x8 *)(&B[swz(row, 2 * half)]);
+            bfr[tn].v[1] = *(const bf16x8 *)(&B[swz(row, 2 * half + 1)]);
+          } else {
+            bfr[tn].v[0] = *(const f32x4 *)(&B[swz(row, 2 * half)]);
+            bfr[tn].v[1] = *(const f32x4 *)(&B[swz(row, 2 * half + 1)]);
+          }
+        }
+#pragma unroll
+        for (int tm = 0; tm < TM; ++tm)
+#pragma unroll
+          for (int tn = 0; tn < TN; ++tn) Mma<T>::mma(acc[tm][tn], af[tm], bfr[tn]);
+      }
+    }
+    if (nx < ns) {
+      if (nnewA) {
+        T *dst = As[nac & 1];
+#pragma unroll
+        for (int i = 0; i < ANV; ++i) {
+          const int v = tid + i * 256;
+          if (v < AROWS * 4) *(uint4 *)(&dst[swz(v >> 2, v & 3)]) = ra[i];
+        }
+      }
+      T *dst = Bs[nx & 1];
+#pragma unroll
+      for (int i = 0; i < BNV; ++i) {
+        const int v = tid + i * 256;
+        if (v < nrows * 4) *(uint4 *)(&dst[swz(v >> 2, v & 3)]) = rb[i];
+      }
+    }
+    __syncthreads();
+  }
+
+  const int cout = a.cout;
+#pragma unroll
+  for (int tm = 0; tm < TM; ++tm)
+#pragma unroll
+    for (int tn = 0; tn < TN; ++tn)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int m = wm * TM * 32 + tm * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+        const int py = y0 + m / PW, px = x0 + m % PW;
+        const int n = n0 + wn * TN * 32 + tn * 32 + l32;
+        if (py >= h || px >= w || n >= cout) continue;
+        const long long pix = (long long)py * w + px;
+        float v = acc[tm][tn][r];
+        if (EPI == EPI_FWD) {
+          v = fmaxf(v + a.bias[n], 0.f);
+          ((T *)a.out)[slot * a.out_ss + pix * cout + n] = from_f<T>(v);
+          if (a.rc) {
+            const float f =
+                a.fc[((long long)(g.gy[t] + py) * a.fc_w + (g.gx[t] + px)) * cout + n];
+            a.rc[slot * a.rc_ss + pix * cout + n] = v - f;
+          }
+        } else {
+          if (a.rc) v += a.two_alpha * a.rc[slot * a.rc_ss + pix * cout + n];
+          if (a.mask) {
+            const float mk = to_f(((const T *)a.mask)[slot * a.mask_ss + pix * cout + n]);
+            if (!(mk > 0.f)) v = 0.f;
+          }
+          ((T *)a.out)[slot * a.out_ss + pix * cout + n] = from_f<T>(v);
+        }
+      }
+}
+
+template <typename T, int BN, int WM, int WN, int EPI, bool SEG2>
+static hipError_t run_conv2(const ConvArgs &a, const Batch &g, hipStream_t s) {
+  const int nblk = g.pfx[g.n];
+  if (nblk == 0) return hipSuccess;
+  dim3 grid(nblk, (a.cout + BN - 1) / BN);
+  hipLaunchKernelGGL((k_conv2<T, BN, WM, WN, EPI, SEG2>), grid, dim3(256), 0, s, a, g);
+  return hipGetLastError();
+}
+
 template <typename T, int PH, int BN, int WM, int WN, int IN, int EPI, bool SEG2>
 static hipError_t run_conv(const ConvArgs &a, const Batch &g, hipStream_t s) {
   const int nblk = g.pfx[g.n];
@@ -246,8 +444,8 @@ static hipError_t run_conv(const ConvArgs &a, const Batch &g, hipStream_t s) {
 
 int conv_block_rows(int precision, int in_mode, int epi, int cout) {
   (void)precision;
-  (void)in_mode;
   if (epi == EPI_STITCH) return 8;
+  if (in_mode == IN_NHWC) return 16;    // k_conv2
   return cout <= 64 ? 16 : 8;
 }
 int conv_block_px(int precision, int in_mode, int epi, int cout) {
@@ -272,16 +470,16 @@ static hipError_t conv_dispatch(int in_mode, int epi, const ConvArgs &a, const B
       return run_conv<T, 16, 64, 4, 1, IN_IMAGE, EPI_FWD, false>(a, g, s);
     }
     if (in_mode != IN_NHWC) return hipErrorInvalidValue;
-    if (small) return run_conv<T, 16, 64, 4, 1, IN_NHWC, EPI_FWD, false>(a, g, s);
-    return run_conv<T, 8, 128, 2, 2, IN_NHWC, EPI_FWD, false>(a, g, s);
+    if (small) return run_conv2<T, 64, 4, 1, EPI_FWD, false>(a, g, s);
+    return run_conv2<T, 128, 2, 2, EPI_FWD, false>(a, g, s);
   }
   // EPI_BWD
   if (in_mode == IN_NHWC) {
     if (small)
-      return seg2 ? run_conv<T, 16, 64, 4, 1, IN_NHWC, EPI_BWD, true>(a, g, s)
-                  : run_conv<T, 16, 64, 4, 1, IN_NHWC, EPI_BWD, false>(a, g, s);
-    return seg2 ? run_conv<T, 8, 128, 2, 2, IN_NHWC, EPI_BWD, true>(a, g, s)
-                : run_conv<T, 8, 128, 2, 2, IN_NHWC, EPI_BWD, false>(a, g, s);
+      return seg2 ? run_conv2<T, 64, 4, 1, EPI_BWD, true>(a, g, s)
+                  : run_conv2<T, 64, 4, 1, EPI_BWD, false>(a, g, s);
+    return seg2 ? run_conv2<T, 128, 2, 2, EPI_BWD, true>(a, g, s)
+                : run_conv2<T, 128, 2, 2, EPI_BWD, false>(a, g, s);
   }
   if (in_mode == IN_NONE) {
     if (small)
@@ -299,6 +497,12 @@ const char *conv_kernel_name(int precision, int in_mode, int epi, const ConvArgs
   char *o = buf[k++ & 7];
   const bool seg2 = a.in2 != nullptr && a.cin2 > 0;
   int ph, bn, wm, wn;
+  if (in_mode == IN_NHWC && epi != EPI_STITCH) {
+    snprintf(o, 160, "void nst::k_conv2<%s, %d, %d, %d, %d, %s>(nst::ConvArgs, nst::Batch)",
+             precision == 1 ? "__bf16" : "float", a.cout <= 64 ? 64 : 128, a.cout <= 64 ? 4 : 2,
+             a.cout <= 64 ? 1 : 2, epi, seg2 ? "true" : "false");
+    return o;
+  }
   if (epi == EPI_STITCH) {
     ph = 8; bn = 32; wm = 4; wn = 1;
   } else if (a.cout <= 64) {

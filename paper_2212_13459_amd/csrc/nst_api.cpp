@@ -157,9 +157,11 @@ struct Layout {
   size_t s_gpart[NST_MAX_STYLE] = {};
 };
 
+// Element offsets are 64-bit everywhere; the 32-bit quantity is a launch's work-item
+// count, at most (window pixels of a layer) x (channels / 4) 16-byte vectors.
 int max_window_ok(const Geom &g, const Layout &L) {
   for (int i = 0; i <= g.top; ++i) {
-    const long long e = (long long)L.lh[i] * L.lw[i] * std::max(g.cout[i], g.cin[i]);
+    const long long e = (long long)L.lh[i] * L.lw[i] * (std::max(g.cout[i], g.cin[i]) / 4 + 1);
     if (e >= (1LL << 31)) return NST_ESHAPE;
   }
   return NST_OK;

@@ -1,0 +1,97 @@
+"""Write FP64 oracle reference values for the full-size workloads (calls oracle/ only).
+
+    python tests/golden/make_golden.py [C2|C3|C4 ...]
+
+For each configuration the oracle evaluates the tiled two-pass loss (Algorithm 1, its
+own planner) on the seeded synthetic inputs and stores, as JSON: the energy terms,
+per-layer Gram summaries of x and of the style image (trace, Frobenius norm, the
+diagonal and the first 8x8 block), content-feature sums, and dE/dx at sampled pixels
+(Step 2 run only on the tiles that hold the samples).  A tiled oracle result equals the
+whole-image one to ~1e-13 (pinned in tests/test_oracle.py), so these are whole-image
+reference values.
+"""
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+import synth  # noqa: E402
+from oracle.loss import energy_terms  # noqa: E402
+from oracle.plan import make_plan  # noqa: E402
+from oracle.tiled import step1, step2, tiled_content_features  # noqa: E402
+
+CONFIGS = {
+    # name: (H, W, Hs, Ws, sigma, T, m, samples per tile, tiles sampled)
+    "C2": dict(H=2048, W=2048, Hs=1024, Ws=1280, sigma=8.0, T=512, m=155),
+    "C3": dict(H=6048, W=8064, Hs=4226, Ws=5319, sigma=16.0, T=1024, m=155),
+    "C4": dict(H=3024, W=4032, Hs=2000, Ws=2000, sigma=16.0, T=1000, m=155),
+}
+W_STYLE = [0.2] * 5
+ALPHA = 1.0
+
+
+def summarize(g):
+    return {"trace": float(np.trace(g)), "fro": float(np.linalg.norm(g)),
+            "diag": [float(v) for v in np.diag(g)], "block8": [[float(v) for v in r] for r in g[:8, :8]]}
+
+
+def sample_pixels(H, W, T, m, seed=4, per_tile=32):
+    """Pixels in two tiles: the one holding the image centre and the last (ragged) one."""
+    net = oracle.vgg19()
+    plan = make_plan(H, W, T, m, net.strides(), net.align())
+    centre = next(k for k, t in enumerate(plan) if t.by0 <= H // 2 < t.by1 and t.bx0 <= W // 2 < t.bx1)
+    picks = sorted({centre, len(plan) - 1})
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in picks:
+        t = plan[k]
+        for _ in range(per_tile):
+            out.append((int(rng.integers(3)), int(rng.integers(t.by0, t.by1)), int(rng.integers(t.bx0, t.bx1))))
+    return picks, out
+
+
+def run(name):
+    cfg = CONFIGS[name]
+    H, W, Hs, Ws, sigma, T, m = (cfg[k] for k in ("H", "W", "Hs", "Ws", "sigma", "T", "m"))
+    t0 = time.time()
+    net = oracle.vgg19()
+    ws, bs = synth.vgg_weights(net.convs, synth.SEED_WEIGHTS)
+    w64 = [w.astype(np.float64) for w in ws]
+    b64 = [b.astype(np.float64) for b in bs]
+    x = synth.image(H, W, sigma, synth.SEED_X).astype(np.float64)
+    c = synth.image(H, W, sigma, synth.SEED_CONTENT).astype(np.float64)
+    s = synth.image(Hs, Ws, sigma, synth.SEED_STYLE).astype(np.float64)
+    print(f"[{name}] inputs {time.time() - t0:.0f}s", flush=True)
+    g_t, _ = step1(net, s, w64, b64, T, m)
+    print(f"[{name}] style grams {time.time() - t0:.0f}s", flush=True)
+    f_c = tiled_content_features(net, c, w64, b64, T, m)
+    print(f"[{name}] content features {time.time() - t0:.0f}s", flush=True)
+    g_x, e_c = step1(net, x, w64, b64, T, m, f_c=f_c, alpha=ALPHA)
+    terms = energy_terms(g_x, g_t, W_STYLE, e_c)
+    print(f"[{name}] step 1 {time.time() - t0:.0f}s E={terms['E']:.9e}", flush=True)
+    picks, px = sample_pixels(H, W, T, m)
+    grad = step2(net, x, w64, g_x, g_t, f_c, W_STYLE, ALPHA, T, m, b64, only=set(picks))
+    print(f"[{name}] step 2 on tiles {picks} {time.time() - t0:.0f}s", flush=True)
+    out = {
+        "config": cfg, "w_style": W_STYLE, "alpha": ALPHA,
+        "E": terms["E"], "E_content": terms["E_content"], "E_style": terms["E_style"],
+        "grams_x": [summarize(g) for g in g_x], "grams_style": [summarize(g) for g in g_t],
+        "content_feats": {"sum": float(f_c.sum()), "sumsq": float((f_c ** 2).sum())},
+        "grad_samples": [[ch, y, xx, float(grad[ch, y, xx])] for ch, y, xx in px],
+        "seconds": time.time() - t0,
+    }
+    with open(os.path.join(HERE, f"oracle_{name}.json"), "w") as f:
+        json.dump(out, f)
+    print(f"[{name}] done in {time.time() - t0:.0f}s", flush=True)
+
+
+if __name__ == "__main__":
+    for name in sys.argv[1:] or ["C2", "C4", "C3"]:
+        run(name)

@@ -44,6 +44,9 @@ def oracle_targets(kind, H, W, Hs, Ws, sigma, bias=0.0):
     return g_t, f_c
 
 
+_records = {}
+
+
 @functools.lru_cache(maxsize=None)
 def oracle_loss(kind, H, W, Hs, Ws, sigma, w_style, alpha, bias=0.0):
     k = case(kind, H, W, Hs, Ws, sigma, bias)
@@ -51,8 +54,23 @@ def oracle_loss(kind, H, W, Hs, Ws, sigma, w_style, alpha, bias=0.0):
     ws = [w.astype(np.float64) for w in k["ws"]]
     bs = [b.astype(np.float64) for b in k["bs"]]
     g_t, f_c = oracle_targets(kind, H, W, Hs, Ws, sigma, bias)
-    terms, grad = loss_grad(net, k["x"].astype(np.float64), ws, bs, g_t, f_c, list(w_style), alpha)
+    rec = {}
+    terms, grad = loss_grad(net, k["x"].astype(np.float64), ws, bs, g_t, f_c, list(w_style), alpha, record=rec)
+    _records[(kind, H, W, Hs, Ws, sigma, w_style, alpha, bias)] = rec
     return terms, grad
+
+
+def flip_corrected(kind, H, W, Hs, Ws, sigma, w_style, alpha, g_test, bias=0.0, delta=1e-5):
+    """Residual of g_test after removing the exact effects of flipped near-tie decisions
+    (decisions whose FP64 margin is below delta x RMS); see oracle.flips."""
+    from oracle.flips import explain
+    terms, g_ref = oracle_loss(kind, H, W, Hs, Ws, sigma, w_style, alpha, bias)
+    rec = _records[(kind, H, W, Hs, Ws, sigma, w_style, alpha, bias)]
+    k = case(kind, H, W, Hs, Ws, sigma, bias)
+    ws = [w.astype(np.float64) for w in k["ws"]]
+    bs = [b.astype(np.float64) for b in k["bs"]]
+    r, acc = explain(k["net"], k["x"].astype(np.float64), ws, bs, rec, g_ref, g_test, delta=delta)
+    return float(np.linalg.norm(r) / np.linalg.norm(g_ref)), acc
 
 
 def flat_grams(gs):

@@ -1,0 +1,181 @@
+"""GPU checks at the workload sizes: the autograd Function, finite differences at
+2048x2048, tiled-vs-whole bit identity at 6048x8064 in the benchmark's launch
+configuration, and sampled comparisons with stored FP64 oracle values
+(tests/golden/oracle_*.json, written by tests/golden/make_golden.py from oracle/ only).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+W5 = [0.2] * 5
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+_ctx = {}
+
+
+@pytest.fixture(autouse=True)
+def release_workspaces():
+    yield
+    for c in _ctx.values():
+        c._ws = {}
+    torch.cuda.empty_cache()
+
+
+def ctx(prec):
+    from paper_2212_13459_amd import Context
+    if prec not in _ctx:
+        ws, bs = synth.vgg_weights(synth.VGG19_CONVS, synth.SEED_WEIGHTS)
+        _ctx[prec] = Context(ws, bs, prec)
+    return _ctx[prec]
+
+
+def images(H, W, Hs, Ws, sigma):
+    dev = torch.device("cuda", 0)
+    x = torch.from_numpy(synth.image(H, W, sigma, synth.SEED_X)).to(dev)
+    c = torch.from_numpy(synth.image(H, W, sigma, synth.SEED_CONTENT)).to(dev)
+    s = torch.from_numpy(synth.image(Hs, Ws, sigma, synth.SEED_STYLE)).to(dev)
+    return x, c, s
+
+
+def rel(a, b):
+    a = np.asarray(a, np.float64).ravel()
+    b = np.asarray(b, np.float64).ravel()
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_autograd_function_equals_loss_grad(prec):
+    from paper_2212_13459_amd import StyleEnergy
+    nst = ctx(prec)
+    x, c, s = images(512, 512, 512, 512, 8.0)
+    gt = nst.style_grams(s, 256, 155)
+    fc = nst.content_feats(c, 256, 155)
+    xv = x.clone().requires_grad_(True)
+    e = StyleEnergy.apply(xv, nst, gt, fc, W5, 1.0, 256, 155)
+    e.backward()
+    e2, _, g2 = nst.loss_grad(x, gt, fc, W5, 1.0, 256, 155)
+    torch.cuda.synchronize()
+    assert e.item() == e2[0]
+    assert torch.equal(xv.grad, g2)
+    # a second backward through a scaled energy scales the gradient
+    xv.grad = None
+    (2.0 * StyleEnergy.apply(xv, nst, gt, fc, W5, 1.0, 256, 155)).backward()
+    assert torch.allclose(xv.grad, 2.0 * g2, rtol=0, atol=0)
+
+
+def test_finite_differences_2048():
+    """Central differences (h = 1e-3) of the FP32 energy at 64 seeded pixels against
+    the autograd gradient, 2048x2048 image, 1024x1280 style, 512 px tiles."""
+    from paper_2212_13459_amd import StyleEnergy
+    from paper_2212_13459_amd.nst import NST_STEP1
+    nst = ctx("fp32")
+    x, c, s = images(2048, 2048, 1024, 1280, 8.0)
+    gt = nst.style_grams(s, 512, 155)
+    fc = nst.content_feats(c, 512, 155)
+    xv = x.clone().requires_grad_(True)
+    StyleEnergy.apply(xv, nst, gt, fc, W5, 1.0, 512, 155).backward()
+    g = xv.grad.double().cpu().numpy()
+    rng = np.random.default_rng(synth.SEED_FD)
+    h = 1e-3
+    fd, an = [], []
+    for _ in range(64):
+        ch, yy, xx = int(rng.integers(3)), int(rng.integers(2048)), int(rng.integers(2048))
+        e = []
+        for sgn in (1.0, -1.0):
+            xp = x.clone()
+            xp[ch, yy, xx] += sgn * h
+            e.append(nst.loss_grad(xp, gt, fc, W5, 1.0, 512, 155, flags=NST_STEP1)[0][0])
+        fd.append((e[0] - e[1]) / (2 * h))
+        an.append(g[ch, yy, xx])
+    fd, an = np.array(fd), np.array(an)
+    err = np.abs(fd - an) / np.maximum(np.abs(an), 0.1 * np.sqrt(np.mean(g ** 2)))
+    print(f"[fd 2048] rel err median {np.median(err):.2e} p90 {np.percentile(err, 90):.2e} max {err.max():.2e} "
+          f"vector rel {rel(fd, an):.2e}", flush=True)
+    assert np.median(err) < 1e-2
+    assert rel(fd, an) < 5e-2
+
+
+def test_full_size_tiled_equals_single_window_bitwise():
+    """6048x8064 with the benchmark's 1024 px tiles vs one 6048x8064 window (BF16): owned
+    features and the fixed-Gram Step 2 gradient are bit-identical."""
+    nst = ctx("bf16")
+    x, c, s = images(6048, 8064, 4226, 5319, 16.0)
+    for conv in (9, 12):
+        a = nst.layer_feats(x, 1024, 155, conv)
+        b = nst.layer_feats(x, 8064, 155, conv)
+        assert torch.equal(a, b), conv
+        del a, b
+    gt = nst.style_grams(s, 1024, 155)
+    fc = nst.content_feats(c, 1024, 155)
+    _, gx, _ = nst.loss_grad(x, gt, fc, W5, 1.0, 1024, 155, flags=1)
+    fixed = gx.clone()
+    _, _, g1 = nst.loss_grad(x, gt, fc, W5, 1.0, 1024, 155, flags=2, grams_x=fixed.clone())
+    g1 = g1.clone()
+    _, _, g2 = nst.loss_grad(x, gt, fc, W5, 1.0, 8064, 155, flags=2, grams_x=fixed.clone())
+    torch.cuda.synchronize()
+    assert torch.equal(g1, g2)
+
+
+def _golden(name):
+    p = os.path.join(HERE, "golden", f"oracle_{name}.json")
+    if not os.path.exists(p):
+        pytest.skip(f"{p} not generated")
+    with open(p) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("name", ["C2", "C4", "C3"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_against_stored_oracle(name, prec):
+    """Energies, Gram summaries, content features and sampled gradient values against the
+    FP64 oracle at the full configuration sizes."""
+    gd = _golden(name)
+    cfg = gd["config"]
+    H, W, Hs, Ws, sigma, T, m = (cfg[k] for k in ("H", "W", "Hs", "Ws", "sigma", "T", "m"))
+    nst = ctx(prec)
+    x, c, s = images(H, W, Hs, Ws, sigma)
+    gt = nst.style_grams(s, T, m)
+    fc = nst.content_feats(c, T, m)
+    energy, gx, grad = nst.loss_grad(x, gt, fc, gd["w_style"], gd["alpha"], T, m)
+    torch.cuda.synchronize()
+    tol_g, tol_e = (1e-5, 1e-5) if prec == "fp32" else (2e-2, 3e-2)
+    gerr = []
+    for G, ref in list(zip(nst.split_grams(gx), gd["grams_x"])) + list(zip(nst.split_grams(gt), gd["grams_style"])):
+        Gn = G.double().cpu().numpy()
+        gerr.append(max(abs(np.trace(Gn) - ref["trace"]) / abs(ref["trace"]),
+                        abs(np.linalg.norm(Gn) - ref["fro"]) / ref["fro"],
+                        rel(np.diag(Gn), ref["diag"]), rel(Gn[:8, :8], ref["block8"])))
+    eerr = [abs(energy[0] - gd["E"]) / gd["E"], abs(energy[1] - gd["E_content"]) / gd["E_content"]]
+    eerr += [abs(a - b) / abs(b) for a, b in zip(energy[2:], gd["E_style"])]
+    f = fc.double()
+    ferr = max(abs(f.sum().item() - gd["content_feats"]["sum"]) / abs(gd["content_feats"]["sum"]),
+               abs((f * f).sum().item() - gd["content_feats"]["sumsq"]) / gd["content_feats"]["sumsq"])
+    smp = np.array(gd["grad_samples"])
+    gv = grad.double().cpu().numpy()[smp[:, 0].astype(int), smp[:, 1].astype(int), smp[:, 2].astype(int)]
+    ref = smp[:, 3]
+    scale = np.sqrt(np.mean(ref ** 2))
+    derr = np.abs(gv - ref) / np.maximum(np.abs(ref), 0.1 * scale)
+    print(f"[golden {name} {prec}] gram summary rel max {max(gerr):.2e}  energy rel {['%.2e' % e for e in eerr]}  "
+          f"content feat sums {ferr:.2e}  grad samples rel median {np.median(derr):.2e} p90 "
+          f"{np.percentile(derr, 90):.2e} vector rel {rel(gv, ref):.2e}", flush=True)
+    assert max(gerr) <= tol_g
+    assert max(eerr) <= tol_e
+    assert ferr <= tol_g
+    if prec == "fp32":
+        assert np.median(derr) <= 1e-4
+    else:
+        assert np.median(derr) <= 0.2

@@ -403,3 +403,81 @@ def test_pins_catch_a_dropped_transpose(monkeypatch):
     monkeypatch.setattr(L, "style_seed", wrong_seed)
     _, bad = L.loss_grad(net, x, ws, bs, g_t, f_c, w_style, 0.0)
     assert rel(bad, tx.grad[0].numpy()) > 1e-3
+
+
+# ------------------------------------------- decision flips (FP32 comparisons) ----
+
+def _recorded_case(h=40, w=44):
+    net, ws, bs, c, s, x, g_t, f_c = _tiny_case(h, w)
+    rec = {}
+    w_style = [1 / 3.0] * 3
+    terms, g = loss_grad(net, x, ws, bs, g_t, f_c, w_style, 1.0, record=rec)
+    acts = [rec[("A", i)] for i in range(net.n_conv)]
+    seeds = {}
+    for k, i in enumerate(net.style):
+        n_p = acts[i].shape[1] * acts[i].shape[2]
+        seeds[i] = style_seed(acts[i], terms["grams"][k], g_t[k], w_style[k], n_p)
+    seeds[net.content] = seeds[net.content] + content_seed(acts[net.content], f_c, 1.0) \
+        if net.content in seeds else content_seed(acts[net.content], f_c, 1.0)
+    return net, ws, bs, x, rec, acts, seeds, g
+
+
+def test_relu_flip_effect_equals_full_backward_difference():
+    from oracle.flips import flip_effect
+    net, ws, bs, x, rec, acts, seeds, g = _recorded_case()
+    i = 2                                          # conv2_1: not followed by a pool
+    c, y, xx = map(int, np.argwhere(acts[i] == 0.0)[17])
+    mod = [a.copy() for a in acts]
+    mod[i][c, y, xx] = 1e-300                      # the mask now passes at this unit
+    g_flip = backward(net, mod, seeds, ws)
+    Y0, Y1, X0, X1, d = flip_effect(net, rec, ws, (0.0, "relu", i, c, y, xx), g.shape[1:])
+    full = np.zeros_like(g)
+    full[:, Y0:Y1, X0:X1] = d
+    assert np.abs(g_flip - g - full).max() <= 1e-12 * np.abs(g).max()
+    assert np.abs(full).max() > 0
+
+
+def test_pool_flip_effect_equals_full_backward_difference():
+    from oracle.flips import flip_effect
+    net, ws, bs, x, rec, acts, seeds, g = _recorded_case()
+    i = 1                                          # pool after conv1_2
+    a = acts[i]
+    h2, w2 = a.shape[1] // 2, a.shape[2] // 2
+    v = np.stack([a[:, dy:2 * h2:2, dx:2 * w2:2] for dy, dx in ((0, 0), (0, 1), (1, 0), (1, 1))], -1)
+    srt = np.sort(v, -1)
+    ok = np.argwhere((srt[..., 2] > 0) & (srt[..., 3] > srt[..., 2]))
+    c, py, px = map(int, ok[5])
+    k1 = int(np.argmax(v[c, py, px]))
+    rest = v[c, py, px].copy()
+    rest[k1] = -np.inf
+    k2 = int(np.argmax(rest))
+    order = ((0, 0), (0, 1), (1, 0), (1, 1))
+    mod = [t.copy() for t in acts]
+    (y1, x1), (y2, x2) = [(2 * py + order[k][0], 2 * px + order[k][1]) for k in (k1, k2)]
+    mod[i][c, y1, x1], mod[i][c, y2, x2] = a[c, y2, x2], a[c, y1, x1]   # routing now goes to k2
+    g_flip = backward(net, mod, seeds, ws)
+    Y0, Y1, X0, X1, d = flip_effect(net, rec, ws, (0.0, "pool", i, c, py, px), g.shape[1:])
+    full = np.zeros_like(g)
+    full[:, Y0:Y1, X0:X1] = d
+    assert np.abs(g_flip - g - full).max() <= 1e-12 * np.abs(g).max()
+    assert np.abs(full).max() > 0
+
+
+def test_explain_removes_planted_flips_and_keeps_real_errors():
+    from oracle.flips import explain, flip_effect, fragile_units
+    net, ws, bs, x, rec, acts, seeds, g = _recorded_case()
+    units = fragile_units(net, acts, ws, bs, x, 1e-3)
+    pick = [units[0], units[3]]
+    g_test = g.copy()
+    for u in pick:
+        Y0, Y1, X0, X1, d = flip_effect(net, rec, ws, u, g.shape[1:])
+        g_test[:, Y0:Y1, X0:X1] += d
+    rng = np.random.default_rng(0)
+    noise = 1e-9 * np.abs(g).max() * rng.standard_normal(g.shape)
+    r, acc = explain(net, x, ws, bs, rec, g, g_test + noise, delta=1e-3)
+    assert rel(r + g, g) < 1e-7
+    # a genuine error (a dropped term) is not explained away
+    bad = g_test.copy()
+    bad[:, 5:9, 5:9] *= 1.5
+    r2, _ = explain(net, x, ws, bs, rec, g, bad, delta=1e-3)
+    assert rel(r2 + g, g) > 1e-3
