@@ -173,7 +173,7 @@ def main():
         "roofline": roofline(args.precision, main_res["stats"], args.steps),
         "effective_mfma_frac": round(FLOP_PER_PX * args.H * args.W / (ms * 1e-3) / 1e12 / peak, 4),
         "kernels": [{k: (round(v, 4) if isinstance(v, float) else v) for k, v in st.items()}
-                    for st in main_res["stats"][:8]],
+                    for st in main_res["stats"]],
         "energy": main_res["energy"],
     }
     if args.fp32_steps > 0 and args.precision != "fp32":

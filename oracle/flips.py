@@ -99,7 +99,28 @@ def flip_effect(net: NetSpec, record, ws, unit, shape):
     ly, lx = qy0 - Y0 // s, qx0 - X0 // s
     A = acts_c[i]
     dz = np.zeros_like(A)
-    if kind == "relu":
+    if kind == "relu" and i in net.pool_after and ("dP", i) in record and \
+            qy // 2 < record[("dP", i)].shape[1] and qx // 2 < record[("dP", i)].shape[2]:
+        # the unit feeds a max pool: flipping it can also move that window's maximum
+        # (e.g. a unit that turns positive in an all-zero window takes the pooled gradient)
+        py, px = qy // 2, qx // 2
+        wy, wx = 2 * py - Y0 // s, 2 * px - X0 // s
+        vals = [A[c, wy + dy, wx + dx] for dy, dx in _ORDER]
+        new = list(vals)
+        k_u = _ORDER.index((qy - 2 * py, qx - 2 * px))
+        new[k_u] = 0.0 if vals[k_u] > 0.0 else np.finfo(np.float64).tiny
+        dp = record[("dP", i)][c, py, px]
+        da_unit = record[("dA", i)][c, qy, qx]
+        for vv, sgn in ((vals, -1.0), (new, 1.0)):
+            k1 = int(np.argmax(vv))
+            for k in range(4):
+                dy, dx = _ORDER[k]
+                g = dp if k == k1 else 0.0
+                if k == k_u:
+                    g += da_unit - (dp if int(np.argmax(vals)) == k_u else 0.0)   # the unit's seed part
+                if vv[k] > 0.0:
+                    dz[c, wy + dy, wx + dx] += sgn * g
+    elif kind == "relu":
         da = record[("dA", i)][c, qy, qx]
         dz[c, ly, lx] = -da if A[c, ly, lx] > 0.0 else da
     else:

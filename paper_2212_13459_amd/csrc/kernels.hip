@@ -244,21 +244,23 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a, Batch g) {
 //   the global loads of stage s+1 are in flight (in registers) while the MFMAs of stage s
 //   run, then land in the other LDS buffer; one barrier per stage.
 //   LDS rows are 64 bytes (four 16-byte chunks) with the chunk index XOR-swizzled by
-//   (row / 2) mod 4, so the 8 lanes of each ds_read_b128 phase hit distinct banks.
+//   (row / 4) mod 4: the 16 lanes of a ds_read_b128 phase read 16 consecutive rows, and
+//   the swizzle sends them to 16 distinct 16-byte bank groups of the 64-bank LDS.
 //   Segment 1 (optional) adds the centre tap over in2 (the style residual V D~).
 // ---------------------------------------------------------------------------------------
 template <typename T, int BN, int WM, int WN, int EPI, bool SEG2>
-__global__ __launch_bounds__(256) void k_conv2(ConvArgs a, Batch g) {
+__global__ __launch_bounds__(WM * WN * 64) void k_conv2(ConvArgs a, Batch g) {
   constexpr int PH = 16, PW = 16, BM = PH * PW;
+  constexpr int NT = WM * WN * 64;
   constexpr int TM = BM / (WM * 32), TN = BN / (WN * 32);
-  static_assert(WM * WN == 4 && TM >= 1 && TN >= 1, "bad wave tiling");
+  static_assert(TM >= 1 && TN >= 1 && TM * WM * 32 == BM && TN * WN * 32 == BN, "bad wave tiling");
   constexpr int CK = Tr<T>::CK;
   constexpr int VEC = 16 / sizeof(T);
   constexpr int HP = PH + 2, WP = PW + 2;
   constexpr int AROWS = HP * WP;
   constexpr int BROWS = 3 * BN;
-  constexpr int ANV = (AROWS * 4 + 255) / 256;
-  constexpr int BNV = (BROWS * 4 + 255) / 256;
+  constexpr int ANV = (AROWS * 4 + NT - 1) / NT;
+  constexpr int BNV = (BROWS * 4 + NT - 1) / NT;
   __shared__ __attribute__((aligned(16))) T As[2][AROWS * CK];
   __shared__ __attribute__((aligned(16))) T Bs[2][BROWS * CK];
 
@@ -273,7 +275,7 @@ __global__ __launch_bounds__(256) void k_conv2(ConvArgs a, Batch g) {
   const int wm = wave / WN, wn = wave % WN;
   const int l32 = lane & 31, half = lane >> 5;
 
-  auto swz = [](int row, int chunk) { return row * CK + ((chunk ^ ((row >> 1) & 3)) * VEC); };
+  auto swz = [](int row, int chunk) { return row * CK + ((chunk ^ ((row >> 2) & 3)) * VEC); };
 
   int pidx[TM];
 #pragma unroll
@@ -312,7 +314,7 @@ __global__ __launch_bounds__(256) void k_conv2(ConvArgs a, Batch g) {
         const int cin = nseg1 ? a.cin2 : a.cin;
 #pragma unroll
         for (int i = 0; i < ANV; ++i) {
-          const int v = tid + i * 256;
+          const int v = tid + i * NT;
           const int pix = v >> 2, part = v & 3;
           const int py = pix / WP, px = pix - py * WP;
           const int yy = y0 - 1 + py, xx = x0 - 1 + px;
@@ -325,7 +327,7 @@ __global__ __launch_bounds__(256) void k_conv2(ConvArgs a, Batch g) {
                     ((long long)nc * (nseg1 ? 1 : 9) + (nseg1 ? 0 : nky * 3)) * a.cout_pad * CK;
 #pragma unroll
       for (int i = 0; i < BNV; ++i) {
-        const int v = tid + i * 256;
+        const int v = tid + i * NT;
         const int row = v >> 2, part = v & 3;
         const int ti = row / BN, n = row - ti * BN;
         const bool ok = v < nrows * 4;
@@ -378,14 +380,14 @@ __global__ __launch_bounds__(256) void k_conv2(ConvArgs a, Batch g) {
         T *dst = As[nac & 1];
 #pragma unroll
         for (int i = 0; i < ANV; ++i) {
-          const int v = tid + i * 256;
+          const int v = tid + i * NT;
           if (v < AROWS * 4) *(uint4 *)(&dst[swz(v >> 2, v & 3)]) = ra[i];
         }
       }
       T *dst = Bs[nx & 1];
 #pragma unroll
       for (int i = 0; i < BNV; ++i) {
-        const int v = tid + i * 256;
+        const int v = tid + i * NT;
         if (v < nrows * 4) *(uint4 *)(&dst[swz(v >> 2, v & 3)]) = rb[i];
       }
     }
@@ -429,8 +431,118 @@ static hipError_t run_conv2(const ConvArgs &a, const Batch &g, hipStream_t s) {
   const int nblk = g.pfx[g.n];
   if (nblk == 0) return hipSuccess;
   dim3 grid(nblk, (a.cout + BN - 1) / BN);
-  hipLaunchKernelGGL((k_conv2<T, BN, WM, WN, EPI, SEG2>), grid, dim3(256), 0, s, a, g);
+  hipLaunchKernelGGL((k_conv2<T, BN, WM, WN, EPI, SEG2>), grid, dim3(WM * WN * 64), 0, s, a, g);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------
+// conv1_1 forward straight from the whole FP32 CHW image (fuses the halo crop).
+//   Work block: a 16 x 16 output patch x all 64 output channels, 4 waves (64 px x 64 ch
+//   each).  Thread t owns pixel t of the patch and writes its im2col row of the 27
+//   (filter tap, colour) values, zero-padded to 32, into LDS; the 64 x 32 weight operand
+//   follows; then K = 32 runs on MFMA and the epilogue applies bias + ReLU.
+// ---------------------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_conv_img(ConvArgs a, Batch g) {
+  constexpr int PW = 16, BM = 256, BN = 64, TM = 2, TN = 2, KP = 32;
+  constexpr int RS = KP + 16 / (int)sizeof(T);         // LDS row stride (elements), 16 B pad
+  __shared__ __attribute__((aligned(16))) T As[BM * RS];
+  __shared__ __attribute__((aligned(16))) T Bs[BN * RS];
+  const int t = find_tile(g, blockIdx.x);
+  const int lb = blockIdx.x - g.pfx[t];
+  const int h = g.h[t], w = g.w[t];
+  const int nbx = (w + PW - 1) / PW;
+  const int y0 = (lb / nbx) * 16, x0 = (lb % nbx) * PW;
+  const long long slot = g.slot[t];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int l32 = lane & 31, half = lane >> 5;
+  {
+    const int py = y0 + (tid >> 4), px = x0 + (tid & 15);
+    T row[KP];
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+      float v = 0.f;
+      if (k < 27) {
+        const int tap = k / 3, c = k - 3 * (k / 3);
+        const int yy = py + tap / 3 - 1, xx = px + tap % 3 - 1;
+        if (py < h && px < w && yy >= 0 && yy < h && xx >= 0 && xx < w)
+          v = a.img[((long long)c * a.img_h + (g.gy[t] + yy)) * a.img_w + (g.gx[t] + xx)];
+      }
+      row[k] = from_f<T>(v);
+    }
+#pragma unroll
+    for (int k = 0; k < KP; ++k) As[tid * RS + k] = row[k];
+    // weight operand: packed [KP / CK][1][64][CK]; row n of B = the 32 k-values of n
+    const T *wp = (const T *)a.wp;
+    constexpr int CK = Tr<T>::CK;
+    for (int e = tid; e < BN * KP; e += 256) {
+      const int n = e / KP, k = e - n * KP;
+      Bs[n * RS + k] = wp[((long long)(k / CK) * a.cout_pad + n) * CK + (k % CK)];
+    }
+  }
+  __syncthreads();
+  f32x16 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+  // lane half g covers k in [16 g, 16 g + 16)
+  typename Mma<T>::Frag af[TM], bfr[TN];
+  if constexpr (sizeof(T) == 2) {
+#pragma unroll
+    for (int tm = 0; tm < TM; ++tm) {
+      const T *p = &As[(wave * 64 + tm * 32 + l32) * RS + half * 16];
+      af[tm].v[0] = *(const bf16x8 *)p;
+      af[tm].v[1] = *(const bf16x8 *)(p + 8);
+    }
+#pragma unroll
+    for (int tn = 0; tn < TN; ++tn) {
+      const T *p = &Bs[(tn * 32 + l32) * RS + half * 16];
+      bfr[tn].v[0] = *(const bf16x8 *)p;
+      bfr[tn].v[1] = *(const bf16x8 *)(p + 8);
+    }
+#pragma unroll
+    for (int tm = 0; tm < TM; ++tm)
+#pragma unroll
+      for (int tn = 0; tn < TN; ++tn) Mma<T>::mma(acc[tm][tn], af[tm], bfr[tn]);
+  } else {
+#pragma unroll
+    for (int hh = 0; hh < 2; ++hh) {
+#pragma unroll
+      for (int tm = 0; tm < TM; ++tm) {
+        const T *p = &As[(wave * 64 + tm * 32 + l32) * RS + half * 16 + hh * 8];
+        af[tm].v[0] = *(const f32x4 *)p;
+        af[tm].v[1] = *(const f32x4 *)(p + 4);
+      }
+#pragma unroll
+      for (int tn = 0; tn < TN; ++tn) {
+        const T *p = &Bs[(tn * 32 + l32) * RS + half * 16 + hh * 8];
+        bfr[tn].v[0] = *(const f32x4 *)p;
+        bfr[tn].v[1] = *(const f32x4 *)(p + 4);
+      }
+#pragma unroll
+      for (int tm = 0; tm < TM; ++tm)
+#pragma unroll
+        for (int tn = 0; tn < TN; ++tn) Mma<T>::mma(acc[tm][tn], af[tm], bfr[tn]);
+    }
+  }
+  const int cout = a.cout;
+#pragma unroll
+  for (int tm = 0; tm < TM; ++tm)
+#pragma unroll
+    for (int tn = 0; tn < TN; ++tn)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int m = wave * 64 + tm * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+        const int py = y0 + m / PW, px = x0 + m % PW;
+        const int n = tn * 32 + l32;
+        if (py >= h || px >= w || n >= cout) continue;
+        const long long pix = (long long)py * w + px;
+        const float v = fmaxf(acc[tm][tn][r] + a.bias[n], 0.f);
+        ((T *)a.out)[slot * a.out_ss + pix * cout + n] = from_f<T>(v);
+      }
 }
 
 template <typename T, int PH, int BN, int WM, int WN, int IN, int EPI, bool SEG2>
@@ -466,20 +578,23 @@ static hipError_t conv_dispatch(int in_mode, int epi, const ConvArgs &a, const B
   if (epi == EPI_FWD) {
     if (seg2) return hipErrorInvalidValue;
     if (in_mode == IN_IMAGE) {
-      if (!small) return hipErrorInvalidValue;
-      return run_conv<T, 16, 64, 4, 1, IN_IMAGE, EPI_FWD, false>(a, g, s);
+      if (a.cout != 64 || a.rc) return hipErrorInvalidValue;
+      const int nblk = g.pfx[g.n];
+      if (nblk == 0) return hipSuccess;
+      hipLaunchKernelGGL(k_conv_img<T>, dim3(nblk), dim3(256), 0, s, a, g);
+      return hipGetLastError();
     }
     if (in_mode != IN_NHWC) return hipErrorInvalidValue;
     if (small) return run_conv2<T, 64, 4, 1, EPI_FWD, false>(a, g, s);
-    return run_conv2<T, 128, 2, 2, EPI_FWD, false>(a, g, s);
+    return run_conv2<T, 128, 4, 2, EPI_FWD, false>(a, g, s);
   }
   // EPI_BWD
   if (in_mode == IN_NHWC) {
     if (small)
       return seg2 ? run_conv2<T, 64, 4, 1, EPI_BWD, true>(a, g, s)
                   : run_conv2<T, 64, 4, 1, EPI_BWD, false>(a, g, s);
-    return seg2 ? run_conv2<T, 128, 2, 2, EPI_BWD, true>(a, g, s)
-                : run_conv2<T, 128, 2, 2, EPI_BWD, false>(a, g, s);
+    return seg2 ? run_conv2<T, 128, 4, 2, EPI_BWD, true>(a, g, s)
+                : run_conv2<T, 128, 4, 2, EPI_BWD, false>(a, g, s);
   }
   if (in_mode == IN_NONE) {
     if (small)
@@ -497,9 +612,13 @@ const char *conv_kernel_name(int precision, int in_mode, int epi, const ConvArgs
   char *o = buf[k++ & 7];
   const bool seg2 = a.in2 != nullptr && a.cin2 > 0;
   int ph, bn, wm, wn;
+  if (in_mode == IN_IMAGE) {
+    snprintf(o, 160, "void nst::k_conv_img<%s>(nst::ConvArgs, nst::Batch)", precision == 1 ? "__bf16" : "float");
+    return o;
+  }
   if (in_mode == IN_NHWC && epi != EPI_STITCH) {
     snprintf(o, 160, "void nst::k_conv2<%s, %d, %d, %d, %d, %s>(nst::ConvArgs, nst::Batch)",
-             precision == 1 ? "__bf16" : "float", a.cout <= 64 ? 64 : 128, a.cout <= 64 ? 4 : 2,
+             precision == 1 ? "__bf16" : "float", a.cout <= 64 ? 64 : 128, 4,
              a.cout <= 64 ? 1 : 2, epi, seg2 ? "true" : "false");
     return o;
   }
@@ -708,6 +827,93 @@ __global__ __launch_bounds__(256) void k_gram(const T *act, long long act_ss, in
   }
 }
 
+// BF16 Gram partials: same chunks and output layout as k_gram, on bf16 MFMA.  A stage of
+// 64 owned pixels is written channel-major into LDS (row = channel, 64 pixels + pad), so
+// that each lane's operand is 8 consecutive pixels of one channel; products are exact in
+// FP32 and accumulate in FP32 within the chunk.  Block CB x CB of the Gram per workgroup,
+// 4 waves in 2 x 2.
+template <int CB>
+__global__ __launch_bounds__(256) void k_gram_bf16(const bf16 *act, long long act_ss, int C,
+                                                   Batch g, float *part, long long part_ss) {
+  constexpr int SP = 64, RS = SP + 8;                  // pixels per stage, LDS row stride
+  constexpr int TB = CB / 64;                           // 32x32 blocks per wave per dim
+  __shared__ __attribute__((aligned(16))) bf16 At[CB * RS];
+  __shared__ __attribute__((aligned(16))) bf16 Bt[CB * RS];
+  const int t = find_tile(g, blockIdx.x);
+  const int k = blockIdx.x - g.pfx[t];
+  const int nb = C / CB;
+  int pair = blockIdx.y, bi = 0;
+  while (pair >= nb - bi) {
+    pair -= nb - bi;
+    ++bi;
+  }
+  const int bj = bi + pair;
+  const bool diag = bi == bj;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int l32 = lane & 31, half = lane >> 5;
+  const int wi = wave >> 1, wj = wave & 1;
+  const int w = g.w[t];
+  const int r0 = g.a0[t], c0 = g.a2[t], c1 = g.a3[t];
+  const int ow = c1 - c0;
+  const int npx = (g.a1[t] - r0) * ow;
+  const int q0 = k * kGramChunk;
+  const int q1 = min(npx, q0 + kGramChunk);
+  const bf16 *b = act + g.slot[t] * act_ss;
+  f32x16 acc[TB][TB];
+#pragma unroll
+  for (int i = 0; i < TB; ++i)
+#pragma unroll
+    for (int j = 0; j < TB; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+  constexpr int NV = SP * CB / 8;                      // 16-byte loads per operand per stage
+  for (int qs = q0; qs < q1; qs += SP) {
+    __syncthreads();
+    for (int v = tid; v < NV * (diag ? 1 : 2); v += 256) {
+      const int op = v >= NV, vv = v - op * NV;
+      const int pl = vv / (CB / 8), cg = vv - pl * (CB / 8);
+      const int q = qs + pl;
+      Vec<bf16> d;
+      d.u = make_uint4(0u, 0u, 0u, 0u);
+      if (q < q1) {
+        const int y = r0 + q / ow, x = c0 + q % ow;
+        d.u = *(const uint4 *)(b + ((long long)y * w + x) * C + (op ? bj : bi) * CB + cg * 8);
+      }
+      bf16 *dst = op ? Bt : At;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) dst[(cg * 8 + j) * RS + pl] = d.e[j];
+    }
+    __syncthreads();
+    const bf16 *Bsrc = diag ? At : Bt;
+#pragma unroll
+    for (int ks = 0; ks < SP / 16; ++ks) {
+      bf16x8 fa[TB], fb[TB];
+#pragma unroll
+      for (int i = 0; i < TB; ++i)
+        fa[i] = *(const bf16x8 *)(&At[(wi * 32 * TB + i * 32 + l32) * RS + ks * 16 + half * 8]);
+#pragma unroll
+      for (int j = 0; j < TB; ++j)
+        fb[j] = *(const bf16x8 *)(&Bsrc[(wj * 32 * TB + j * 32 + l32) * RS + ks * 16 + half * 8]);
+#pragma unroll
+      for (int i = 0; i < TB; ++i)
+#pragma unroll
+        for (int j = 0; j < TB; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
+    }
+  }
+  float *o = part + g.slot[t] * part_ss + (long long)k * C * C;
+#pragma unroll
+  for (int i = 0; i < TB; ++i)
+#pragma unroll
+    for (int j = 0; j < TB; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int ii = bi * CB + wi * 32 * TB + i * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+        const int jj = bj * CB + wj * 32 * TB + j * 32 + l32;
+        o[(long long)ii * C + jj] = acc[i][j][r];
+      }
+}
+
 // tilesum[t][i][j] = sum over the tile's chunks (in order) of part[.][k][min(i,j)][max(i,j)]
 __global__ __launch_bounds__(256) void k_gram_tile_reduce(const float *part, long long part_ss,
                                                           int C, Batch g, double *tilesum) {
@@ -736,11 +942,22 @@ hipError_t launch_gram(int precision, const void *act, long long act_ss, int C, 
                        float *part, long long part_ss, hipStream_t s) {
   const int nblk = g.pfx[g.n];
   if (nblk == 0) return hipSuccess;
+  if (precision == 1) {
+    const int cb = C >= 128 ? 128 : 64;
+    const int nb = C / cb;
+    dim3 grid(nblk, nb * (nb + 1) / 2);
+    if (cb == 128)
+      hipLaunchKernelGGL(k_gram_bf16<128>, grid, dim3(256), 0, s, (const bf16 *)act, act_ss, C, g,
+                         part, part_ss);
+    else
+      hipLaunchKernelGGL(k_gram_bf16<64>, grid, dim3(256), 0, s, (const bf16 *)act, act_ss, C, g,
+                         part, part_ss);
+    return hipGetLastError();
+  }
   const int nb = C / 64;
   dim3 grid(nblk, nb * (nb + 1) / 2);
-  if (precision == 1)
-    hipLaunchKernelGGL(k_gram<bf16>, grid, dim3(256), 0, s, (const bf16 *)act, act_ss, C, g,
-                       part, part_ss);
+  if (false)
+    ;
   else
     hipLaunchKernelGGL(k_gram<float>, grid, dim3(256), 0, s, (const float *)act, act_ss, C, g,
                        part, part_ss);

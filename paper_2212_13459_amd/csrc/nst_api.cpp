@@ -661,7 +661,8 @@ struct Runner {
       float *part = (float *)slot_base(L.s_gpart[k]);
       double npx = 0;
       for (int t = 0; t < n; ++t) npx += (double)items[t];
-      HIPCHK(prof(c->prec == 1 ? "void nst::k_gram<__bf16>(__bf16 const*, long long, int, nst::Batch, float*, long long)"
+      HIPCHK(prof(c->prec == 1 ? (C >= 128 ? "void nst::k_gram_bf16<128>(__bf16 const*, long long, int, nst::Batch, float*, long long)"
+                                           : "void nst::k_gram_bf16<64>(__bf16 const*, long long, int, nst::Batch, float*, long long)")
                                : "void nst::k_gram<float>(float const*, long long, int, nst::Batch, float*, long long)",
                   2.0 * npx * C * C, npx * C * L.es, [&] {
                     return launch_gram(c->prec, slot_base(L.s_act[i]), ss(L.es), C, b, part, ss(4), s);

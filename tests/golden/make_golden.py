@@ -25,6 +25,8 @@ import oracle  # noqa: E402
 import synth  # noqa: E402
 from oracle.loss import energy_terms  # noqa: E402
 from oracle.plan import make_plan  # noqa: E402
+from oracle.loss import forward  # noqa: E402
+from oracle.net import receptive_fields  # noqa: E402
 from oracle.tiled import step1, step2, tiled_content_features  # noqa: E402
 
 CONFIGS = {
@@ -57,6 +59,58 @@ def sample_pixels(H, W, T, m, seed=4, per_tile=32):
     return picks, out
 
 
+def local_fd(net, x, w64, b64, g_x, g_t, f_c, px, h=1e-3):
+    """Central differences (E(x + h e) - E(x - h e)) / 2h of the FP64 energy for single
+    pixels, evaluated exactly from a window around the pixel: a pixel changes only the
+    features whose dependency cone [s q - a, s q + b] contains it, so with the global
+    Grams G(x) the energy change is
+        sum_l w_l (||D_l + (S+ - S0)/n_p||^2 - ||D_l + (S- - S0)/n_p||^2)
+        + alpha sum (||v+ - f||^2 - ||v- - f||^2)
+    with D_l = G_l(x) - Ghat_l and S the V^T V sums over those features."""
+    H, W = x.shape[1:]
+    S = net.align()
+    rf = receptive_fields(net)
+    strides = net.strides()
+    top = max(list(net.style) + [net.content])
+    d = [gx - gt for gx, gt in zip(g_x, g_t)]
+    out = []
+    for ch, y, xx in px:
+        Y0, Y1 = max(0, S * ((y - 160) // S)), min(H, S * (-(-(y + 161) // S)))
+        X0, X1 = max(0, S * ((xx - 160) // S)), min(W, S * (-(-(xx + 161) // S)))
+        win = x[:, Y0:Y1, X0:X1]
+        acts = {}
+        for key, sgn in (("0", 0.0), ("+", 1.0), ("-", -1.0)):
+            xw = win.copy()
+            xw[ch, y - Y0, xx - X0] += sgn * h
+            acts[key] = forward(net, xw, w64, b64, upto=top)
+        e = {}
+        for key in ("+", "-"):
+            tot = 0.0
+            for k, i in enumerate(net.style):
+                s, (a, b) = strides[i], rf[i]
+                n_h, n_w = H // s, W // s
+                r0, r1 = max(0, -(-(y - b) // s)), min(n_h - 1, (y + a) // s) + 1
+                c0, c1 = max(0, -(-(xx - b) // s)), min(n_w - 1, (xx + a) // s) + 1
+                oy, ox = Y0 // s, X0 // s
+                sums = []
+                for kk in (key, "0"):
+                    v = acts[kk][i][:, r0 - oy:r1 - oy, c0 - ox:c1 - ox].reshape(acts[kk][i].shape[0], -1)
+                    sums.append(v @ v.T)
+                n_p = float(n_h * n_w)
+                tot += W_STYLE[k] * float(np.sum((d[k] + (sums[0] - sums[1]) / n_p) ** 2))
+            i = net.content
+            s, (a, b) = strides[i], rf[i]
+            n_h, n_w = H // s, W // s
+            r0, r1 = max(0, -(-(y - b) // s)), min(n_h - 1, (y + a) // s) + 1
+            c0, c1 = max(0, -(-(xx - b) // s)), min(n_w - 1, (xx + a) // s) + 1
+            oy, ox = Y0 // s, X0 // s
+            v = acts[key][i][:, r0 - oy:r1 - oy, c0 - ox:c1 - ox]
+            tot += ALPHA * float(np.sum((v - f_c[:, r0:r1, c0:c1]) ** 2))
+            e[key] = tot
+        out.append((e["+"] - e["-"]) / (2 * h))
+    return out
+
+
 def run(name):
     cfg = CONFIGS[name]
     H, W, Hs, Ws, sigma, T, m = (cfg[k] for k in ("H", "W", "Hs", "Ws", "sigma", "T", "m"))
@@ -79,12 +133,15 @@ def run(name):
     picks, px = sample_pixels(H, W, T, m)
     grad = step2(net, x, w64, g_x, g_t, f_c, W_STYLE, ALPHA, T, m, b64, only=set(picks))
     print(f"[{name}] step 2 on tiles {picks} {time.time() - t0:.0f}s", flush=True)
+    fd = local_fd(net, x, w64, b64, g_x, g_t, f_c, px) if name == "C2" else None
+    print(f"[{name}] finite differences {time.time() - t0:.0f}s", flush=True)
     out = {
         "config": cfg, "w_style": W_STYLE, "alpha": ALPHA,
         "E": terms["E"], "E_content": terms["E_content"], "E_style": terms["E_style"],
         "grams_x": [summarize(g) for g in g_x], "grams_style": [summarize(g) for g in g_t],
         "content_feats": {"sum": float(f_c.sum()), "sumsq": float((f_c ** 2).sum())},
         "grad_samples": [[ch, y, xx, float(grad[ch, y, xx])] for ch, y, xx in px],
+        "fd_h": 1e-3, "fd_samples": fd,
         "seconds": time.time() - t0,
     }
     with open(os.path.join(HERE, f"oracle_{name}.json"), "w") as f:

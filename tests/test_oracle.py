@@ -481,3 +481,31 @@ def test_explain_removes_planted_flips_and_keeps_real_errors():
     bad[:, 5:9, 5:9] *= 1.5
     r2, _ = explain(net, x, ws, bs, rec, g, bad, delta=1e-3)
     assert rel(r2 + g, g) > 1e-3
+
+
+def test_relu_flip_into_all_zero_pool_window():
+    """A unit that turns positive inside an all-zero pooling window becomes that window's
+    maximum and takes the pooled gradient: flip_effect must match a full backward."""
+    from oracle.flips import flip_effect
+    net, ws, bs, x, rec, acts, seeds, g = _recorded_case()
+    i = 1                                          # conv1_2, followed by pool1
+    a = acts[i]
+    h2, w2 = a.shape[1] // 2, a.shape[2] // 2
+    v = np.stack([a[:, dy:2 * h2:2, dx:2 * w2:2] for dy, dx in ((0, 0), (0, 1), (1, 0), (1, 1))], -1)
+    zero = np.argwhere(v.max(-1) == 0.0)
+    found = None
+    for c, py, px in zero:
+        if rec[("dP", i)][c, py, px] != 0.0:
+            found = (int(c), int(py), int(px))
+            break
+    assert found is not None
+    c, py, px = found
+    y, xx = 2 * py + 1, 2 * px                       # third position in window order
+    mod = [t.copy() for t in acts]
+    mod[i][c, y, xx] = 1e-300                      # now the (only) positive value of the window
+    g_flip = backward(net, mod, seeds, ws)
+    Y0, Y1, X0, X1, d = flip_effect(net, rec, ws, (0.0, "relu", i, c, y, xx), g.shape[1:])
+    full = np.zeros_like(g)
+    full[:, Y0:Y1, X0:X1] = d
+    assert np.abs(g_flip - g - full).max() <= 1e-12 * np.abs(g).max()
+    assert np.abs(full).max() > 0
