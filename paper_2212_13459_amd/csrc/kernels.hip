@@ -19,6 +19,7 @@ namespace nst {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16;
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
@@ -248,6 +249,91 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a, Batch g) {
 //   the swizzle sends them to 16 distinct 16-byte bank groups of the 64-bank LDS.
 //   Segment 1 (optional) adds the centre tap over in2 (the style residual V D~).
 // ---------------------------------------------------------------------------------------
+// Branch-free stage loads: every lane loads from a valid (clamped) address and selects
+// zero outside the window, so the compiler can track the in-flight loads exactly and
+// overlap them with the MFMAs of the current stage.
+template <typename T, int NT, int ANV, int WP, int CK, int VEC>
+__device__ __forceinline__ void stage_load_a(u32x4 (&ra)[ANV], const T *src, int cin, int c, int y0,
+                                             int x0, int h, int w, int tid) {
+#pragma unroll
+  for (int i = 0; i < ANV; ++i) {
+    const int v = tid + i * NT;
+    const int pix = v >> 2, part = v & 3;
+    const int py = pix / WP, px = pix - py * WP;
+    const int yy = y0 - 1 + py, xx = x0 - 1 + px;
+    const bool ok = yy >= 0 && yy < h && xx >= 0 && xx < w;
+    const int cy = min(max(yy, 0), h - 1), cx = min(max(xx, 0), w - 1);
+    const u32x4 val = *(const u32x4 *)(src + ((long long)cy * w + cx) * cin + c * CK + part * VEC);
+    const unsigned m = ok ? 0xffffffffu : 0u;
+    ra[i] = val & m;
+  }
+}
+
+template <typename T, int NT, int BNV, int BN, int CK, int VEC>
+__device__ __forceinline__ void stage_load_b(u32x4 (&rb)[BNV], const T *wb, int cout_pad, int n0,
+                                             int ntap_rows, int tid) {
+#pragma unroll
+  for (int i = 0; i < BNV; ++i) {
+    const int v = tid + i * NT;
+    const int row = v >> 2, part = v & 3;
+    int ti = row / BN;
+    const int n = row - ti * BN;
+    ti = ti < ntap_rows ? ti : 0;            // rows past the stage's taps duplicate tap 0 (unused)
+    rb[i] = *(const u32x4 *)(wb + ((long long)ti * cout_pad + n0 + n) * CK + part * VEC);
+  }
+}
+
+__device__ __forceinline__ int swz64(int row, int chunk, int ck, int vec) {
+  return row * ck + ((chunk ^ ((row >> 2) & 3)) * vec);
+}
+
+template <typename T, int NT, int NV, int CK, int VEC>
+__device__ __forceinline__ void stage_store(T *dst, const u32x4 (&r)[NV], int tid) {
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    const int v = tid + i * NT;
+    *(u32x4 *)(&dst[swz64(v >> 2, v & 3, CK, VEC)]) = r[i];
+  }
+}
+
+// MFMAs of one stage: ntap taps at LDS pixel offsets toff0 + ti.
+template <typename T, int TM, int TN, int BN, int CK, int VEC>
+__device__ __forceinline__ void stage_mma(f32x16 (&acc)[TM][TN], const T *A, const T *B,
+                                          const int (&pidx)[TM], int toff0, int ntap, int bcol,
+                                          int half) {
+#pragma unroll 1
+  for (int ti = 0; ti < ntap; ++ti) {
+    const int toff = toff0 + ti;
+    typename Mma<T>::Frag af[TM], bfr[TN];
+#pragma unroll
+    for (int tm = 0; tm < TM; ++tm) {
+      const int row = pidx[tm] + toff;
+      if constexpr (sizeof(T) == 2) {
+        af[tm].v[0] = *(const bf16x8 *)(&A[swz64(row, 2 * half, CK, VEC)]);
+        af[tm].v[1] = *(const bf16x8 *)(&A[swz64(row, 2 * half + 1, CK, VEC)]);
+      } else {
+        af[tm].v[0] = *(const f32x4 *)(&A[swz64(row, 2 * half, CK, VEC)]);
+        af[tm].v[1] = *(const f32x4 *)(&A[swz64(row, 2 * half + 1, CK, VEC)]);
+      }
+    }
+#pragma unroll
+    for (int tn = 0; tn < TN; ++tn) {
+      const int row = ti * BN + bcol + tn * 32;
+      if constexpr (sizeof(T) == 2) {
+        bfr[tn].v[0] = *(const bf16x8 *)(&B[swz64(row, 2 * half, CK, VEC)]);
+        bfr[tn].v[1] = *(const bf16x8 *)(&B[swz64(row, 2 * half + 1, CK, VEC)]);
+      } else {
+        bfr[tn].v[0] = *(const f32x4 *)(&B[swz64(row, 2 * half, CK, VEC)]);
+        bfr[tn].v[1] = *(const f32x4 *)(&B[swz64(row, 2 * half + 1, CK, VEC)]);
+      }
+    }
+#pragma unroll
+    for (int tm = 0; tm < TM; ++tm)
+#pragma unroll
+      for (int tn = 0; tn < TN; ++tn) Mma<T>::mma(acc[tm][tn], af[tm], bfr[tn]);
+  }
+}
+
 template <typename T, int BN, int WM, int WN, int EPI, bool SEG2>
 __global__ __launch_bounds__(WM * WN * 64) void k_conv2(ConvArgs a, Batch g) {
   constexpr int PH = 16, PW = 16, BM = PH * PW;
@@ -261,8 +347,10 @@ __global__ __launch_bounds__(WM * WN * 64) void k_conv2(ConvArgs a, Batch g) {
   constexpr int BROWS = 3 * BN;
   constexpr int ANV = (AROWS * 4 + NT - 1) / NT;
   constexpr int BNV = (BROWS * 4 + NT - 1) / NT;
-  __shared__ __attribute__((aligned(16))) T As[2][AROWS * CK];
-  __shared__ __attribute__((aligned(16))) T Bs[2][BROWS * CK];
+  constexpr int AROWS_P = ANV * NT / 4;         // padded so every thread's store lands in the buffer
+  constexpr int BROWS_P = BNV * NT / 4;
+  __shared__ __attribute__((aligned(16))) T As[2][AROWS_P * CK];
+  __shared__ __attribute__((aligned(16))) T Bs[2][BROWS_P * CK];
 
   const int t = find_tile(g, blockIdx.x);
   const int lb = blockIdx.x - g.pfx[t];
@@ -274,8 +362,6 @@ __global__ __launch_bounds__(WM * WN * 64) void k_conv2(ConvArgs a, Batch g) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / WN, wn = wave % WN;
   const int l32 = lane & 31, half = lane >> 5;
-
-  auto swz = [](int row, int chunk) { return row * CK + ((chunk ^ ((row >> 2) & 3)) * VEC); };
 
   int pidx[TM];
 #pragma unroll
@@ -292,106 +378,70 @@ __global__ __launch_bounds__(WM * WN * 64) void k_conv2(ConvArgs a, Batch g) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
-  const int n0s = (a.cin / CK) * 3;
-  const int ns = n0s + (SEG2 ? a.cin2 / CK : 0);
-  uint4 ra[ANV], rb[BNV];
+  const T *in0 = (const T *)a.in + slot * a.in_ss;
+  const T *in1 = SEG2 ? (const T *)a.in2 + slot * a.in2_ss : nullptr;
+  const T *wp0 = (const T *)a.wp;
+  const T *wp1 = (const T *)a.wp2;
+  const int nck = a.cin / CK;
+  const int nck2 = SEG2 ? a.cin2 / CK : 0;
+  u32x4 ra[ANV], rb[BNV];
 
-  // Iteration st: issue the global loads of stage st+1 into registers, run the MFMAs of
-  // stage st from LDS, then write the registers to the other LDS buffers.
+  // stage (c, ky) of segment 0 uses A buffer c & 1 and B buffer (3 c + ky) & 1; segment-1
+  // chunk c2 is stage 3 nck + c2 with A buffer (nck + c2) & 1.
+  stage_load_a<T, NT, ANV, WP, CK, VEC>(ra, in0, a.cin, 0, y0, x0, h, w, tid);
+  stage_load_b<T, NT, BNV, BN, CK, VEC>(rb, wp0, a.cout_pad, n0, 3, tid);
+  stage_store<T, NT, ANV, CK, VEC>(As[0], ra, tid);
+  stage_store<T, NT, BNV, CK, VEC>(Bs[0], rb, tid);
+  __syncthreads();
 #pragma unroll 1
-  for (int st = -1; st < ns; ++st) {
-    const int nx = st + 1;
-    // decode stage nx: segment, chunk, filter row, A-buffer counter
-    const bool nseg1 = nx >= n0s;
-    const int nc = nseg1 ? nx - n0s : nx / 3;
-    const int nky = nseg1 ? 1 : nx - 3 * nc;
-    const int nac = nseg1 ? n0s / 3 + nc : nc;
-    const bool nnewA = nseg1 || nky == 0;
-    const int nrows = nseg1 ? BN : BROWS;
-    if (nx < ns) {
-      if (nnewA) {
-        const T *src = (const T *)(nseg1 ? a.in2 : a.in) + slot * (nseg1 ? a.in2_ss : a.in_ss);
-        const int cin = nseg1 ? a.cin2 : a.cin;
-#pragma unroll
-        for (int i = 0; i < ANV; ++i) {
-          const int v = tid + i * NT;
-          const int pix = v >> 2, part = v & 3;
-          const int py = pix / WP, px = pix - py * WP;
-          const int yy = y0 - 1 + py, xx = x0 - 1 + px;
-          const bool ok = v < AROWS * 4 && yy >= 0 && yy < h && xx >= 0 && xx < w;
-          const T *p = src + ((long long)(ok ? yy : 0) * w + (ok ? xx : 0)) * cin + nc * CK + part * VEC;
-          ra[i] = ok ? *(const uint4 *)p : make_uint4(0u, 0u, 0u, 0u);
-        }
-      }
-      const T *wb = (const T *)(nseg1 ? a.wp2 : a.wp) +
-                    ((long long)nc * (nseg1 ? 1 : 9) + (nseg1 ? 0 : nky * 3)) * a.cout_pad * CK;
-#pragma unroll
-      for (int i = 0; i < BNV; ++i) {
-        const int v = tid + i * NT;
-        const int row = v >> 2, part = v & 3;
-        const int ti = row / BN, n = row - ti * BN;
-        const bool ok = v < nrows * 4;
-        const T *p = wb + ((long long)(ok ? ti : 0) * a.cout_pad + n0 + (ok ? n : 0)) * CK + part * VEC;
-        rb[i] = ok ? *(const uint4 *)p : make_uint4(0u, 0u, 0u, 0u);
-      }
+  for (int c = 0; c < nck; ++c) {
+    const int ab = c & 1, s0 = 3 * c;
+    // filter row 0; prefetch row 1 (weights only)
+    stage_load_b<T, NT, BNV, BN, CK, VEC>(rb, wp0 + ((long long)c * 9 + 3) * a.cout_pad * CK,
+                                          a.cout_pad, n0, 3, tid);
+    stage_mma<T, TM, TN, BN, CK, VEC>(acc, As[ab], Bs[s0 & 1], pidx, 0, 3, wn * TN * 32 + l32, half);
+    stage_store<T, NT, BNV, CK, VEC>(Bs[(s0 + 1) & 1], rb, tid);
+    __syncthreads();
+    // filter row 1; prefetch row 2
+    stage_load_b<T, NT, BNV, BN, CK, VEC>(rb, wp0 + ((long long)c * 9 + 6) * a.cout_pad * CK,
+                                          a.cout_pad, n0, 3, tid);
+    stage_mma<T, TM, TN, BN, CK, VEC>(acc, As[ab], Bs[(s0 + 1) & 1], pidx, WP, 3, wn * TN * 32 + l32, half);
+    stage_store<T, NT, BNV, CK, VEC>(Bs[(s0 + 2) & 1], rb, tid);
+    __syncthreads();
+    // filter row 2; prefetch the next chunk's halo patch and row 0 (or segment 1)
+    const bool more = c + 1 < nck;
+    if (more) {
+      stage_load_a<T, NT, ANV, WP, CK, VEC>(ra, in0, a.cin, c + 1, y0, x0, h, w, tid);
+      stage_load_b<T, NT, BNV, BN, CK, VEC>(rb, wp0 + (long long)(c + 1) * 9 * a.cout_pad * CK,
+                                            a.cout_pad, n0, 3, tid);
+    } else if (SEG2 && nck2 > 0) {
+      stage_load_a<T, NT, ANV, WP, CK, VEC>(ra, in1, a.cin2, 0, y0, x0, h, w, tid);
+      stage_load_b<T, NT, BNV, BN, CK, VEC>(rb, wp1, a.cout_pad, n0, 1, tid);
     }
-    if (st >= 0) {
-      const bool seg1 = st >= n0s;
-      const int c = seg1 ? st - n0s : st / 3;
-      const int ky = seg1 ? 1 : st - 3 * c;
-      const int ac = seg1 ? n0s / 3 + c : c;
-      const T *A = As[ac & 1];
-      const T *B = Bs[st & 1];
-      const int ntap = seg1 ? 1 : 3;
-#pragma unroll 1
-      for (int ti = 0; ti < ntap; ++ti) {
-        const int toff = seg1 ? WP + 1 : ky * WP + ti;
-        typename Mma<T>::Frag af[TM], bfr[TN];
-#pragma unroll
-        for (int tm = 0; tm < TM; ++tm) {
-          const int row = pidx[tm] + toff;
-          if constexpr (sizeof(T) == 2) {
-            af[tm].v[0] = *(const bf16x8 *)(&A[swz(row, 2 * half)]);
-            af[tm].v[1] = *(const bf16x8 *)(&A[swz(row, 2 * half + 1)]);
-          } else {
-            af[tm].v[0] = *(const f32x4 *)(&A[swz(row, 2 * half)]);
-            af[tm].v[1] = *(const f32x4 *)(&A[swz(row, 2 * half + 1)]);
-          }
-        }
-#pragma unroll
-        for (int tn = 0; tn < TN; ++tn) {
-          const int row = ti * BN + wn * TN * 32 + tn * 32 + l32;
-          if constexpr (sizeof(T) == 2) {
-            bfr[tn].v[0] = *(const bf16x8 *)(&B[swz(row, 2 * half)]);
-            bfr[tn].v[1] = *(const bf16x8 *)(&B[swz(row, 2 * half + 1)]);
-          } else {
-            bfr[tn].v[0] = *(const f32x4 *)(&B[swz(row, 2 * half)]);
-            bfr[tn].v[1] = *(const f32x4 *)(&B[swz(row, 2 * half + 1)]);
-          }
-        }
-#pragma unroll
-        for (int tm = 0; tm < TM; ++tm)
-#pragma unroll
-          for (int tn = 0; tn < TN; ++tn) Mma<T>::mma(acc[tm][tn], af[tm], bfr[tn]);
-      }
-    }
-    if (nx < ns) {
-      if (nnewA) {
-        T *dst = As[nac & 1];
-#pragma unroll
-        for (int i = 0; i < ANV; ++i) {
-          const int v = tid + i * NT;
-          if (v < AROWS * 4) *(uint4 *)(&dst[swz(v >> 2, v & 3)]) = ra[i];
-        }
-      }
-      T *dst = Bs[nx & 1];
-#pragma unroll
-      for (int i = 0; i < BNV; ++i) {
-        const int v = tid + i * NT;
-        if (v < nrows * 4) *(uint4 *)(&dst[swz(v >> 2, v & 3)]) = rb[i];
-      }
+    stage_mma<T, TM, TN, BN, CK, VEC>(acc, As[ab], Bs[(s0 + 2) & 1], pidx, 2 * WP, 3, wn * TN * 32 + l32, half);
+    if (more || (SEG2 && nck2 > 0)) {
+      stage_store<T, NT, ANV, CK, VEC>(As[(c + 1) & 1], ra, tid);
+      stage_store<T, NT, BNV, CK, VEC>(Bs[(s0 + 3) & 1], rb, tid);
     }
     __syncthreads();
+  }
+  if constexpr (SEG2) {
+#pragma unroll 1
+    for (int c2 = 0; c2 < nck2; ++c2) {
+      const int st = 3 * nck + c2, ac = nck + c2;
+      const bool more = c2 + 1 < nck2;
+      if (more) {
+        stage_load_a<T, NT, ANV, WP, CK, VEC>(ra, in1, a.cin2, c2 + 1, y0, x0, h, w, tid);
+        stage_load_b<T, NT, BNV, BN, CK, VEC>(rb, wp1 + (long long)(c2 + 1) * a.cout_pad * CK,
+                                              a.cout_pad, n0, 1, tid);
+      }
+      stage_mma<T, TM, TN, BN, CK, VEC>(acc, As[ac & 1], Bs[st & 1], pidx, WP + 1, 1, wn * TN * 32 + l32, half);
+      if (more) {
+        stage_store<T, NT, ANV, CK, VEC>(As[(ac + 1) & 1], ra, tid);
+        stage_store<T, NT, BNV, CK, VEC>(Bs[(st + 1) & 1], rb, tid);
+      }
+      __syncthreads();
+    }
   }
 
   const int cout = a.cout;
