@@ -636,6 +636,7 @@ static hipError_t conv_dispatch(int in_mode, int epi, const ConvArgs &a, const B
     }
     if (in_mode != IN_NHWC) return hipErrorInvalidValue;
     if (small) return run_conv2<T, 64, 4, 1, EPI_FWD, false>(a, g, s);
+    if (a.cout % 256 == 0) return run_conv2<T, 256, 2, 4, EPI_FWD, false>(a, g, s);
     return run_conv2<T, 128, 4, 2, EPI_FWD, false>(a, g, s);
   }
   // EPI_BWD
@@ -643,6 +644,9 @@ static hipError_t conv_dispatch(int in_mode, int epi, const ConvArgs &a, const B
     if (small)
       return seg2 ? run_conv2<T, 64, 4, 1, EPI_BWD, true>(a, g, s)
                   : run_conv2<T, 64, 4, 1, EPI_BWD, false>(a, g, s);
+    if (a.cout % 256 == 0)
+      return seg2 ? run_conv2<T, 256, 2, 4, EPI_BWD, true>(a, g, s)
+                  : run_conv2<T, 256, 2, 4, EPI_BWD, false>(a, g, s);
     return seg2 ? run_conv2<T, 128, 4, 2, EPI_BWD, true>(a, g, s)
                 : run_conv2<T, 128, 4, 2, EPI_BWD, false>(a, g, s);
   }
@@ -667,9 +671,10 @@ const char *conv_kernel_name(int precision, int in_mode, int epi, const ConvArgs
     return o;
   }
   if (in_mode == IN_NHWC && epi != EPI_STITCH) {
+    const int bn = a.cout <= 64 ? 64 : (a.cout % 256 == 0 ? 256 : 128);
+    const int wm = bn == 256 ? 2 : 4, wn = bn == 64 ? 1 : (bn == 256 ? 4 : 2);
     snprintf(o, 160, "void nst::k_conv2<%s, %d, %d, %d, %d, %s>(nst::ConvArgs, nst::Batch)",
-             precision == 1 ? "__bf16" : "float", a.cout <= 64 ? 64 : 128, 4,
-             a.cout <= 64 ? 1 : 2, epi, seg2 ? "true" : "false");
+             precision == 1 ? "__bf16" : "float", bn, wm, wn, epi, seg2 ? "true" : "false");
     return o;
   }
   if (epi == EPI_STITCH) {
