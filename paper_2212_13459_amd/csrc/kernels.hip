@@ -296,42 +296,62 @@ __device__ __forceinline__ void stage_store(T *dst, const u32x4 (&r)[NV], int ti
   }
 }
 
-// MFMAs of one stage: ntap taps at LDS pixel offsets toff0 + ti.
+// MFMAs of one filter tap at LDS pixel offset toff.
 template <typename T, int TM, int TN, int BN, int CK, int VEC>
-__device__ __forceinline__ void stage_mma(f32x16 (&acc)[TM][TN], const T *A, const T *B,
-                                          const int (&pidx)[TM], int toff0, int ntap, int bcol,
-                                          int half) {
-#pragma unroll 1
-  for (int ti = 0; ti < ntap; ++ti) {
-    const int toff = toff0 + ti;
-    typename Mma<T>::Frag af[TM], bfr[TN];
+__device__ __forceinline__ void tap_mma(f32x16 (&acc)[TM][TN], const T *A, const T *B,
+                                        const int (&pidx)[TM], int toff, int ti, int bcol, int half) {
+  typename Mma<T>::Frag af[TM], bfr[TN];
 #pragma unroll
-    for (int tm = 0; tm < TM; ++tm) {
-      const int row = pidx[tm] + toff;
-      if constexpr (sizeof(T) == 2) {
-        af[tm].v[0] = *(const bf16x8 *)(&A[swz64(row, 2 * half, CK, VEC)]);
-        af[tm].v[1] = *(const bf16x8 *)(&A[swz64(row, 2 * half + 1, CK, VEC)]);
-      } else {
-        af[tm].v[0] = *(const f32x4 *)(&A[swz64(row, 2 * half, CK, VEC)]);
-        af[tm].v[1] = *(const f32x4 *)(&A[swz64(row, 2 * half + 1, CK, VEC)]);
-      }
+  for (int tm = 0; tm < TM; ++tm) {
+    const int row = pidx[tm] + toff;
+    if constexpr (sizeof(T) == 2) {
+      af[tm].v[0] = *(const bf16x8 *)(&A[swz64(row, 2 * half, CK, VEC)]);
+      af[tm].v[1] = *(const bf16x8 *)(&A[swz64(row, 2 * half + 1, CK, VEC)]);
+    } else {
+      af[tm].v[0] = *(const f32x4 *)(&A[swz64(row, 2 * half, CK, VEC)]);
+      af[tm].v[1] = *(const f32x4 *)(&A[swz64(row, 2 * half + 1, CK, VEC)]);
     }
-#pragma unroll
-    for (int tn = 0; tn < TN; ++tn) {
-      const int row = ti * BN + bcol + tn * 32;
-      if constexpr (sizeof(T) == 2) {
-        bfr[tn].v[0] = *(const bf16x8 *)(&B[swz64(row, 2 * half, CK, VEC)]);
-        bfr[tn].v[1] = *(const bf16x8 *)(&B[swz64(row, 2 * half + 1, CK, VEC)]);
-      } else {
-        bfr[tn].v[0] = *(const f32x4 *)(&B[swz64(row, 2 * half, CK, VEC)]);
-        bfr[tn].v[1] = *(const f32x4 *)(&B[swz64(row, 2 * half + 1, CK, VEC)]);
-      }
-    }
-#pragma unroll
-    for (int tm = 0; tm < TM; ++tm)
-#pragma unroll
-      for (int tn = 0; tn < TN; ++tn) Mma<T>::mma(acc[tm][tn], af[tm], bfr[tn]);
   }
+#pragma unroll
+  for (int tn = 0; tn < TN; ++tn) {
+    const int row = ti * BN + bcol + tn * 32;
+    if constexpr (sizeof(T) == 2) {
+      bfr[tn].v[0] = *(const bf16x8 *)(&B[swz64(row, 2 * half, CK, VEC)]);
+      bfr[tn].v[1] = *(const bf16x8 *)(&B[swz64(row, 2 * half + 1, CK, VEC)]);
+    } else {
+      bfr[tn].v[0] = *(const f32x4 *)(&B[swz64(row, 2 * half, CK, VEC)]);
+      bfr[tn].v[1] = *(const f32x4 *)(&B[swz64(row, 2 * half + 1, CK, VEC)]);
+    }
+  }
+#pragma unroll
+  for (int tm = 0; tm < TM; ++tm)
+#pragma unroll
+    for (int tn = 0; tn < TN; ++tn) Mma<T>::mma(acc[tm][tn], af[tm], bfr[tn]);
+}
+
+// MFMAs of one stage: NTAP taps at LDS pixel offsets toff0 + ti.  UNR unrolls the taps so
+// the fragment loads of one tap can overlap the MFMAs of the previous one (needed when a
+// SIMD runs a single wave).
+template <typename T, int TM, int TN, int BN, int CK, int VEC, int NTAP, bool UNR>
+__device__ __forceinline__ void stage_mma(f32x16 (&acc)[TM][TN], const T *A, const T *B,
+                                          const int (&pidx)[TM], int toff0, int bcol, int half) {
+  if constexpr (UNR) {
+#pragma unroll
+    for (int ti = 0; ti < NTAP; ++ti)
+      tap_mma<T, TM, TN, BN, CK, VEC>(acc, A, B, pidx, toff0 + ti, ti, bcol, half);
+  } else {
+#pragma unroll 1
+    for (int ti = 0; ti < NTAP; ++ti)
+      tap_mma<T, TM, TN, BN, CK, VEC>(acc, A, B, pidx, toff0 + ti, ti, bcol, half);
+  }
+}
+
+// Passes of the LDS epilogue: the fewest that divide TN and fit the FP32 tile
+// (BM x (WN x TN / passes x 32 + 8) floats) into the stage buffers.
+constexpr int epi_passes(int bm, int wn, int tn, int smem_bytes) {
+  for (int p = 1; p <= tn; ++p)
+    if (tn % p == 0 && bm * (wn * (tn / p) * 32 + 8) * 4 <= smem_bytes) return p;
+  return 0;
 }
 
 template <typename T, int BN, int WM, int WN, int EPI, bool SEG2>
@@ -349,8 +369,13 @@ __global__ __launch_bounds__(WM * WN * 64) void k_conv2(ConvArgs a, Batch g) {
   constexpr int BNV = (BROWS * 4 + NT - 1) / NT;
   constexpr int AROWS_P = ANV * NT / 4;         // padded so every thread's store lands in the buffer
   constexpr int BROWS_P = BNV * NT / 4;
-  __shared__ __attribute__((aligned(16))) T As[2][AROWS_P * CK];
-  __shared__ __attribute__((aligned(16))) T Bs[2][BROWS_P * CK];
+  constexpr int ASZ = AROWS_P * CK, BSZ = BROWS_P * CK;
+  static_assert(epi_passes(BM, WN, TN, 2 * (ASZ + BSZ) * (int)sizeof(T)) > 0, "epilogue does not fit");
+  // wide wave tiles (one wave per SIMD): accumulators in AGPRs, taps unrolled
+  constexpr bool WIDE = TM * TN >= 16;
+  constexpr bool UNRT = false;
+  __shared__ __attribute__((aligned(16))) T sm[2 * (ASZ + BSZ)];
+  if constexpr (WIDE) asm volatile("" ::: "a0");
 
   const int t = find_tile(g, blockIdx.x);
   const int lb = blockIdx.x - g.pfx[t];
@@ -390,8 +415,8 @@ __global__ __launch_bounds__(WM * WN * 64) void k_conv2(ConvArgs a, Batch g) {
   // chunk c2 is stage 3 nck + c2 with A buffer (nck + c2) & 1.
   stage_load_a<T, NT, ANV, WP, CK, VEC>(ra, in0, a.cin, 0, y0, x0, h, w, tid);
   stage_load_b<T, NT, BNV, BN, CK, VEC>(rb, wp0, a.cout_pad, n0, 3, tid);
-  stage_store<T, NT, ANV, CK, VEC>(As[0], ra, tid);
-  stage_store<T, NT, BNV, CK, VEC>(Bs[0], rb, tid);
+  stage_store<T, NT, ANV, CK, VEC>((sm + ASZ * (0)), ra, tid);
+  stage_store<T, NT, BNV, CK, VEC>((sm + 2 * ASZ + BSZ * (0)), rb, tid);
   __syncthreads();
 #pragma unroll 1
   for (int c = 0; c < nck; ++c) {
@@ -399,14 +424,14 @@ __global__ __launch_bounds__(WM * WN * 64) void k_conv2(ConvArgs a, Batch g) {
     // filter row 0; prefetch row 1 (weights only)
     stage_load_b<T, NT, BNV, BN, CK, VEC>(rb, wp0 + ((long long)c * 9 + 3) * a.cout_pad * CK,
                                           a.cout_pad, n0, 3, tid);
-    stage_mma<T, TM, TN, BN, CK, VEC>(acc, As[ab], Bs[s0 & 1], pidx, 0, 3, wn * TN * 32 + l32, half);
-    stage_store<T, NT, BNV, CK, VEC>(Bs[(s0 + 1) & 1], rb, tid);
+    stage_mma<T, TM, TN, BN, CK, VEC, 3, UNRT>(acc, (sm + ASZ * (ab)), (sm + 2 * ASZ + BSZ * (s0 & 1)), pidx, 0, wn * TN * 32 + l32, half);
+    stage_store<T, NT, BNV, CK, VEC>((sm + 2 * ASZ + BSZ * ((s0 + 1) & 1)), rb, tid);
     __syncthreads();
     // filter row 1; prefetch row 2
     stage_load_b<T, NT, BNV, BN, CK, VEC>(rb, wp0 + ((long long)c * 9 + 6) * a.cout_pad * CK,
                                           a.cout_pad, n0, 3, tid);
-    stage_mma<T, TM, TN, BN, CK, VEC>(acc, As[ab], Bs[(s0 + 1) & 1], pidx, WP, 3, wn * TN * 32 + l32, half);
-    stage_store<T, NT, BNV, CK, VEC>(Bs[(s0 + 2) & 1], rb, tid);
+    stage_mma<T, TM, TN, BN, CK, VEC, 3, UNRT>(acc, (sm + ASZ * (ab)), (sm + 2 * ASZ + BSZ * ((s0 + 1) & 1)), pidx, WP, wn * TN * 32 + l32, half);
+    stage_store<T, NT, BNV, CK, VEC>((sm + 2 * ASZ + BSZ * ((s0 + 2) & 1)), rb, tid);
     __syncthreads();
     // filter row 2; prefetch the next chunk's halo patch and row 0 (or segment 1)
     const bool more = c + 1 < nck;
@@ -418,10 +443,10 @@ __global__ __launch_bounds__(WM * WN * 64) void k_conv2(ConvArgs a, Batch g) {
       stage_load_a<T, NT, ANV, WP, CK, VEC>(ra, in1, a.cin2, 0, y0, x0, h, w, tid);
       stage_load_b<T, NT, BNV, BN, CK, VEC>(rb, wp1, a.cout_pad, n0, 1, tid);
     }
-    stage_mma<T, TM, TN, BN, CK, VEC>(acc, As[ab], Bs[(s0 + 2) & 1], pidx, 2 * WP, 3, wn * TN * 32 + l32, half);
+    stage_mma<T, TM, TN, BN, CK, VEC, 3, UNRT>(acc, (sm + ASZ * (ab)), (sm + 2 * ASZ + BSZ * ((s0 + 2) & 1)), pidx, 2 * WP, wn * TN * 32 + l32, half);
     if (more || (SEG2 && nck2 > 0)) {
-      stage_store<T, NT, ANV, CK, VEC>(As[(c + 1) & 1], ra, tid);
-      stage_store<T, NT, BNV, CK, VEC>(Bs[(s0 + 3) & 1], rb, tid);
+      stage_store<T, NT, ANV, CK, VEC>((sm + ASZ * ((c + 1) & 1)), ra, tid);
+      stage_store<T, NT, BNV, CK, VEC>((sm + 2 * ASZ + BSZ * ((s0 + 3) & 1)), rb, tid);
     }
     __syncthreads();
   }
@@ -435,45 +460,96 @@ __global__ __launch_bounds__(WM * WN * 64) void k_conv2(ConvArgs a, Batch g) {
         stage_load_b<T, NT, BNV, BN, CK, VEC>(rb, wp1 + (long long)(c2 + 1) * a.cout_pad * CK,
                                               a.cout_pad, n0, 1, tid);
       }
-      stage_mma<T, TM, TN, BN, CK, VEC>(acc, As[ac & 1], Bs[st & 1], pidx, WP + 1, 1, wn * TN * 32 + l32, half);
+      stage_mma<T, TM, TN, BN, CK, VEC, 1, UNRT>(acc, (sm + ASZ * (ac & 1)), (sm + 2 * ASZ + BSZ * (st & 1)), pidx, WP + 1, wn * TN * 32 + l32, half);
       if (more) {
-        stage_store<T, NT, ANV, CK, VEC>(As[(ac + 1) & 1], ra, tid);
-        stage_store<T, NT, BNV, CK, VEC>(Bs[(st + 1) & 1], rb, tid);
+        stage_store<T, NT, ANV, CK, VEC>((sm + ASZ * ((ac + 1) & 1)), ra, tid);
+        stage_store<T, NT, BNV, CK, VEC>((sm + 2 * ASZ + BSZ * ((st + 1) & 1)), rb, tid);
       }
       __syncthreads();
     }
   }
 
+  // Epilogue through LDS (the last stage barrier has released the stage buffers), in
+  // NPASS passes over the wave's TN column blocks: phase 1 writes the raw FP32
+  // accumulators of the pass, phase 2 reads VEC consecutive channels of one pixel and
+  // applies bias + ReLU (+ content difference) or content residual + ReLU mask with
+  // 16-byte loads and stores.  The arithmetic per element is the same as applying it to
+  // the accumulator directly.
+  constexpr int NPASS = epi_passes(BM, WN, TN, 2 * (ASZ + BSZ) * (int)sizeof(T));
+  constexpr int TNP = TN / NPASS, CW = TNP * 32, RSW = WN * CW + 8;
+  constexpr int CPR = WN * CW / VEC;
+  static_assert((BM * CPR) % NT == 0, "epilogue tiling");
+  typedef T TV __attribute__((ext_vector_type(VEC)));
+  float *so = (float *)sm;
   const int cout = a.cout;
 #pragma unroll
-  for (int tm = 0; tm < TM; ++tm)
+  for (int p = 0; p < NPASS; ++p) {
+    if (p > 0) __syncthreads();
 #pragma unroll
-    for (int tn = 0; tn < TN; ++tn)
+    for (int tm = 0; tm < TM; ++tm)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int m = wm * TM * 32 + tm * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
-        const int py = y0 + m / PW, px = x0 + m % PW;
-        const int n = n0 + wn * TN * 32 + tn * 32 + l32;
-        if (py >= h || px >= w || n >= cout) continue;
-        const long long pix = (long long)py * w + px;
-        float v = acc[tm][tn][r];
-        if (EPI == EPI_FWD) {
-          v = fmaxf(v + a.bias[n], 0.f);
-          ((T *)a.out)[slot * a.out_ss + pix * cout + n] = from_f<T>(v);
-          if (a.rc) {
-            const float f =
-                a.fc[((long long)(g.gy[t] + py) * a.fc_w + (g.gx[t] + px)) * cout + n];
-            a.rc[slot * a.rc_ss + pix * cout + n] = v - f;
+      for (int tq = 0; tq < TNP; ++tq)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int m = wm * TM * 32 + tm * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+          so[m * RSW + wn * CW + tq * 32 + l32] = acc[tm][p * TNP + tq][r];
+        }
+    __syncthreads();
+#pragma unroll 2
+    for (int i = 0; i < BM * CPR / NT; ++i) {
+      const int idx = tid + i * NT;
+      const int m = idx / CPR, lc = (idx % CPR) * VEC;
+      const int n = n0 + (lc / CW) * TN * 32 + p * CW + lc % CW;
+      const int py = y0 + m / PW, px = x0 + m % PW;
+      if (py >= h || px >= w || n >= cout) continue;
+      const long long pix = (long long)py * w + px;
+      float v[VEC];
+#pragma unroll
+      for (int q = 0; q < VEC / 4; ++q) {
+        const f32x4 u = *(const f32x4 *)(&so[m * RSW + lc + 4 * q]);
+        v[4 * q] = u[0]; v[4 * q + 1] = u[1]; v[4 * q + 2] = u[2]; v[4 * q + 3] = u[3];
+      }
+      if (EPI == EPI_FWD) {
+#pragma unroll
+        for (int q = 0; q < VEC / 4; ++q) {
+          const f32x4 b = *(const f32x4 *)(a.bias + n + 4 * q);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) v[4 * q + e] = fmaxf(v[4 * q + e] + b[e], 0.f);
+        }
+        if (a.rc) {
+          const float *f = a.fc + ((long long)(g.gy[t] + py) * a.fc_w + (g.gx[t] + px)) * cout + n;
+          float *rc = a.rc + slot * a.rc_ss + pix * cout + n;
+#pragma unroll
+          for (int q = 0; q < VEC / 4; ++q) {
+            f32x4 d;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) d[e] = v[4 * q + e] - f[4 * q + e];
+            *(f32x4 *)(rc + 4 * q) = d;
           }
-        } else {
-          if (a.rc) v += a.two_alpha * a.rc[slot * a.rc_ss + pix * cout + n];
-          if (a.mask) {
-            const float mk = to_f(((const T *)a.mask)[slot * a.mask_ss + pix * cout + n]);
-            if (!(mk > 0.f)) v = 0.f;
+        }
+      } else {
+        if (a.rc) {
+          const float *rc = a.rc + slot * a.rc_ss + pix * cout + n;
+#pragma unroll
+          for (int q = 0; q < VEC / 4; ++q) {
+            const f32x4 d = *(const f32x4 *)(rc + 4 * q);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) v[4 * q + e] += a.two_alpha * d[e];
           }
-          ((T *)a.out)[slot * a.out_ss + pix * cout + n] = from_f<T>(v);
+        }
+        if (a.mask) {
+          const TV mk = *(const TV *)((const T *)a.mask + slot * a.mask_ss + pix * cout + n);
+#pragma unroll
+          for (int e = 0; e < VEC; ++e)
+            if (!(to_f(mk[e]) > 0.f)) v[e] = 0.f;
         }
       }
+      TV o;
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) o[e] = from_f<T>(v[e]);
+      *(TV *)((T *)a.out + slot * a.out_ss + pix * cout + n) = o;
+    }
+  }
 }
 
 template <typename T, int BN, int WM, int WN, int EPI, bool SEG2>
@@ -636,7 +712,10 @@ static hipError_t conv_dispatch(int in_mode, int epi, const ConvArgs &a, const B
     }
     if (in_mode != IN_NHWC) return hipErrorInvalidValue;
     if (small) return run_conv2<T, 64, 4, 1, EPI_FWD, false>(a, g, s);
-    if (a.cout % 256 == 0) return run_conv2<T, 256, 2, 4, EPI_FWD, false>(a, g, s);
+    if (a.cout % 256 == 0) {
+      if constexpr (sizeof(T) == 2) return run_conv2<T, 256, 2, 2, EPI_FWD, false>(a, g, s);
+      else return run_conv2<T, 256, 2, 4, EPI_FWD, false>(a, g, s);
+    }
     return run_conv2<T, 128, 4, 2, EPI_FWD, false>(a, g, s);
   }
   // EPI_BWD
@@ -644,9 +723,14 @@ static hipError_t conv_dispatch(int in_mode, int epi, const ConvArgs &a, const B
     if (small)
       return seg2 ? run_conv2<T, 64, 4, 1, EPI_BWD, true>(a, g, s)
                   : run_conv2<T, 64, 4, 1, EPI_BWD, false>(a, g, s);
-    if (a.cout % 256 == 0)
-      return seg2 ? run_conv2<T, 256, 2, 4, EPI_BWD, true>(a, g, s)
-                  : run_conv2<T, 256, 2, 4, EPI_BWD, false>(a, g, s);
+    if (a.cout % 256 == 0) {
+      if constexpr (sizeof(T) == 2)
+        return seg2 ? run_conv2<T, 256, 2, 2, EPI_BWD, true>(a, g, s)
+                    : run_conv2<T, 256, 2, 2, EPI_BWD, false>(a, g, s);
+      else
+        return seg2 ? run_conv2<T, 256, 2, 4, EPI_BWD, true>(a, g, s)
+                    : run_conv2<T, 256, 2, 4, EPI_BWD, false>(a, g, s);
+    }
     return seg2 ? run_conv2<T, 128, 4, 2, EPI_BWD, true>(a, g, s)
                 : run_conv2<T, 128, 4, 2, EPI_BWD, false>(a, g, s);
   }
@@ -672,7 +756,8 @@ const char *conv_kernel_name(int precision, int in_mode, int epi, const ConvArgs
   }
   if (in_mode == IN_NHWC && epi != EPI_STITCH) {
     const int bn = a.cout <= 64 ? 64 : (a.cout % 256 == 0 ? 256 : 128);
-    const int wm = bn == 256 ? 2 : 4, wn = bn == 64 ? 1 : (bn == 256 ? 4 : 2);
+    const int wm = bn == 256 ? 2 : 4;
+    const int wn = bn == 64 ? 1 : (bn == 256 ? (precision == 1 ? 2 : 4) : 2);
     snprintf(o, 160, "void nst::k_conv2<%s, %d, %d, %d, %d, %s>(nst::ConvArgs, nst::Batch)",
              precision == 1 ? "__bf16" : "float", bn, wm, wn, epi, seg2 ? "true" : "false");
     return o;
