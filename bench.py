@@ -83,6 +83,7 @@ def run_precision(prec, steps, warmup, args, x, c, s, ws, bs, profile):
 
 
 def roofline(prec, stats, steps):
+    from paper_2212_13459_amd.profsum import read_traffic
     top = stats[0]
     avg_ms = top["ms"] / top["launches"]
     if top["flops"] > 0:
@@ -93,8 +94,16 @@ def roofline(prec, stats, steps):
         achieved = top["bytes"] / top["launches"] / (avg_ms * 1e-3) / 1e9
         peak = HBM_GBS
         r = {"bound": "hbm", "achieved": round(achieved, 1), "peak": peak, "unit": "GB/s"}
-    r.update({"frac": round(achieved / peak, 4), "traffic": None, "kernel": top["name"],
-              "launches_per_step": top["launches"] / steps, "avg_launch_ms": round(avg_ms, 4)})
+    # HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE summary, if it was
+    # taken on the current kernel sources
+    tr = read_traffic(os.path.join(ROOT, "profiles"), top["name"])
+    r.update({"frac": round(achieved / peak, 4), "traffic": None if tr is None else round(tr[0]),
+              "kernel": top["name"], "launches_per_step": top["launches"] / steps,
+              "avg_launch_ms": round(avg_ms, 4),
+              "algorithmic_bytes_per_launch": round(top["bytes"] / top["launches"]),
+              "algorithmic_flops_per_launch": round(top["flops"] / top["launches"])})
+    if tr is not None:
+        r["traffic_source"] = tr[1]
     return r
 
 
@@ -144,6 +153,9 @@ def main():
     ap.add_argument("--ws-gib", type=float, default=120.0)
     ap.add_argument("--cpu-sample", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="first launch a plain copy (negation) kernel of this many MiB three times, "
+                         "as the reference for FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -156,6 +168,15 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     from paper_2212_13459_amd import plan, vgg19_desc
     n_tiles = len(plan(vgg19_desc(), args.H, args.W, args.T, args.m))
+    if args.copy_calibration_mib > 0:
+        n = args.copy_calibration_mib << 18
+        a = torch.ones(n, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            torch.neg(a, out=b)
+        torch.cuda.synchronize()
+        log(f"[bench] copy calibration: 3 x {4 * n} bytes read and written")
+        del a, b
     x, c, s, ws, bs = make_inputs(args)
 
     main_res = run_precision(args.precision, args.steps, args.warmup, args, x, c, s, ws, bs, profile=True)

@@ -1,0 +1,215 @@
+"""Text summaries of rocprofv3 output for the kernels of libnst.
+
+    python -m paper_2212_13459_amd.profsum stats  STATS_CSV [--top N] [--cmd "..."]
+    python -m paper_2212_13459_amd.profsum traffic FETCH_OUT WRITE_OUT --kernel NAME
+           --copy-bytes B [--cmd-fetch "..."] [--cmd-write "..."]
+
+``stats`` formats a ``--kernel-trace --stats`` kernel_stats.csv.  ``traffic`` turns two
+``--pmc FETCH_SIZE`` / ``--pmc WRITE_SIZE`` runs (counter_collection.csv or *_results.db)
+into HBM bytes per launch of one kernel.  Each counter is scaled by what it reads for a
+plain copy kernel of B bytes read and B bytes written in the same run (the
+elementwise negation kernel that bench.py --copy-calibration-mib launches), so that the
+figure is in the same units as the algorithmic bytes.  The summary records a digest of
+the kernel sources; bench.py reports the traffic only while the digest still matches.
+"""
+import argparse
+import collections
+import csv
+import glob
+import hashlib
+import os
+import sqlite3
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SOURCES = ("csrc/kernels.hip", "csrc/kernels.h", "csrc/nst_api.cpp")
+COPY_KERNEL = "neg_kernel"
+
+
+def demangle(names):
+    """Demangled kernel names.  rocprofv3 leaves names with a __bf16 template argument
+    mangled (its demangler does not know DF16b); spelled as the vendor type u6__bf16
+    they demangle to the same text as the library's own profile records."""
+    names = list(names)
+    todo = [n for n in names if n.startswith("_Z")]
+    if not todo:
+        return {n: n for n in names}
+    out = subprocess.run(["c++filt"], input="\n".join(t.replace("DF16b", "u6__bf16") for t in todo),
+                         capture_output=True, text=True, check=True).stdout.split("\n")
+    m = {n: n for n in names}
+    m.update(zip(todo, out))
+    return m
+
+
+def source_digest():
+    h = hashlib.sha256()
+    for rel in SOURCES:
+        with open(os.path.join(HERE, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def _find(path, pattern):
+    if os.path.isfile(path):
+        return path
+    hits = sorted(glob.glob(os.path.join(path, "**", pattern), recursive=True))
+    if not hits:
+        raise FileNotFoundError(f"no {pattern} under {path}")
+    return hits[0]
+
+
+def read_counters(path):
+    """{kernel name: {counter: [value per dispatch, in dispatch order]}} from a --pmc run."""
+    out = collections.defaultdict(lambda: collections.defaultdict(dict))
+    try:
+        f = _find(path, "*counter_collection.csv")
+        with open(f) as fh:
+            for row in csv.DictReader(fh):
+                out[row["Kernel_Name"]][row["Counter_Name"]][int(row["Dispatch_Id"])] = \
+                    out[row["Kernel_Name"]][row["Counter_Name"]].get(int(row["Dispatch_Id"]), 0.0) + \
+                    float(row["Counter_Value"])
+    except FileNotFoundError:
+        f = _find(path, "*_results.db")
+        con = sqlite3.connect(f)
+        for k, c, v, d in con.execute(
+                "select kernel_name, counter_name, value, dispatch_id from counters_collection"):
+            out[k][c][d] = out[k][c].get(d, 0.0) + float(v)
+    dm = demangle(out)
+    return {dm[k]: {c: [d[i] for i in sorted(d)] for c, d in cs.items()} for k, cs in out.items()}
+
+
+def _pick(counters, needle):
+    names = [k for k in counters if needle in k]
+    if not names:
+        raise KeyError(f"kernel {needle!r} not in the counter output ({len(counters)} kernels)")
+    return max(names, key=lambda k: len(next(iter(counters[k].values()))))
+
+
+def traffic(fetch_path, write_path, kernel, copy_bytes, last=0):
+    """HBM bytes per launch of ``kernel``, averaged over its last ``last`` dispatches (all
+    of them if 0)."""
+    fc, wc = read_counters(fetch_path), read_counters(write_path)
+    res = {}
+    for tag, cs, cname in (("fetch", fc, "FETCH_SIZE"), ("write", wc, "WRITE_SIZE")):
+        k = _pick(cs, kernel)
+        cp = _pick(cs, COPY_KERNEL)
+        vals, cvals = cs[k][cname], cs[cp][cname]
+        if last:
+            vals = vals[-last:]
+        per = sum(vals) / len(vals)
+        cper = sum(cvals) / len(cvals)
+        scale = copy_bytes / 1024.0 / cper
+        res[tag] = dict(kernel=kernel, rocprof_name=k, dispatches=len(vals), kib_per_dispatch=per, copy_kib=cper,
+                        copy_kernel=cp, scale=scale, bytes_per_launch=per * scale * 1024.0)
+    return res
+
+
+def write_traffic(res, copy_bytes, cmd_fetch, cmd_write, out):
+    f, w = res["fetch"], res["write"]
+    total = f["bytes_per_launch"] + w["bytes_per_launch"]
+    lines = [
+        f"# HBM traffic of {f['kernel']}",
+        "",
+        f"command (FETCH_SIZE): {cmd_fetch}",
+        f"command (WRITE_SIZE): {cmd_write}",
+        "",
+        f"kernel: {f['kernel']}",
+        f"rocprof kernel name: {f['rocprof_name']}",
+        f"source_digest: {source_digest()}",
+        f"dispatches averaged (the last ones, the benchmark's loss+gradient evaluations): {f['dispatches']}",
+        f"FETCH_SIZE KiB per dispatch (raw): {f['kib_per_dispatch']:.1f}",
+        f"WRITE_SIZE KiB per dispatch (raw): {w['kib_per_dispatch']:.1f}",
+        f"copy kernel: {f['copy_kernel']} reading and writing {copy_bytes} bytes per dispatch",
+        f"copy FETCH_SIZE KiB (raw): {f['copy_kib']:.1f}  scale {f['scale']:.4f}",
+        f"copy WRITE_SIZE KiB (raw): {w['copy_kib']:.1f}  scale {w['scale']:.4f}",
+        f"fetch_bytes_per_launch: {f['bytes_per_launch']:.0f}",
+        f"write_bytes_per_launch: {w['bytes_per_launch']:.0f}",
+        f"traffic_bytes_per_launch: {total:.0f}",
+    ]
+    text = "\n".join(lines) + "\n"
+    if out:
+        with open(out, "w") as fh:
+            fh.write(text)
+    return text
+
+
+def read_traffic(profiles_dir, kernel):
+    """HBM bytes per launch of ``kernel`` from a summary whose digest matches the current
+    sources, else None."""
+    dig = source_digest()
+    for p in sorted(glob.glob(os.path.join(profiles_dir, "*traffic*.txt"))):
+        kv = {}
+        with open(p) as fh:
+            for line in fh:
+                if ": " in line and not line.startswith("#"):
+                    a, b = line.rstrip("\n").split(": ", 1)
+                    kv[a] = b
+        if kv.get("kernel") == kernel and kv.get("source_digest") == dig:
+            return float(kv["traffic_bytes_per_launch"]), os.path.basename(p)
+    return None
+
+
+def last_dispatches(path, kernel, n):
+    """Mean duration (ms) of the last n dispatches of ``kernel`` in kernel_trace.csv."""
+    f = _find(path, "*kernel_trace.csv")
+    d = []
+    with open(f) as fh:
+        rows = list(csv.DictReader(fh))
+    dm = demangle({r["Kernel_Name"] for r in rows})
+    for row in rows:
+        if kernel in dm[row["Kernel_Name"]]:
+            d.append((int(row["Start_Timestamp"]), int(row["End_Timestamp"]) - int(row["Start_Timestamp"])))
+    d.sort()
+    tail = [x[1] for x in d[-n:]]
+    return len(d), sum(tail) / len(tail) / 1e6
+
+
+def stats(path, top, cmd, kernel="", last=0):
+    f = _find(path, "*kernel_stats.csv")
+    with open(f) as fh:
+        rows = list(csv.DictReader(fh))
+    dm = demangle({r["Name"] for r in rows})
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    lines = [f"command: {cmd}", "",
+             "| kernel | calls | total ms | average ms | min ms | max ms | % |",
+             "|---|---:|---:|---:|---:|---:|---:|"]
+    for r in rows[:top]:
+        lines.append(f"| `{dm[r['Name']][:110]}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
+                     f"{float(r['AverageNs']) / 1e6:.4f} | {float(r['MinNs']) / 1e6:.4f} | "
+                     f"{float(r['MaxNs']) / 1e6:.4f} | {float(r['Percentage']):.2f} |")
+    if kernel and last:
+        total, avg = last_dispatches(path, kernel, last)
+        lines += ["", f"`{kernel}`: {total} dispatches in the run; mean of the last {last} "
+                      f"(the last evaluations, all of the benchmark's configuration): {avg:.4f} ms"]
+    return "\n".join(lines) + "\n"
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="mode", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("path")
+    s.add_argument("--top", type=int, default=25)
+    s.add_argument("--cmd", default="")
+    s.add_argument("--kernel", default="")
+    s.add_argument("--last", type=int, default=0)
+    t = sub.add_parser("traffic")
+    t.add_argument("fetch")
+    t.add_argument("write")
+    t.add_argument("--kernel", required=True)
+    t.add_argument("--copy-bytes", type=int, required=True)
+    t.add_argument("--cmd-fetch", default="")
+    t.add_argument("--cmd-write", default="")
+    t.add_argument("--out", default="")
+    t.add_argument("--last", type=int, default=0)
+    a = ap.parse_args(argv)
+    if a.mode == "stats":
+        sys.stdout.write(stats(a.path, a.top, a.cmd, a.kernel, a.last))
+    else:
+        res = traffic(a.fetch, a.write, a.kernel, a.copy_bytes, a.last)
+        sys.stdout.write(write_traffic(res, a.copy_bytes, a.cmd_fetch, a.cmd_write, a.out))
+
+
+if __name__ == "__main__":
+    main()
