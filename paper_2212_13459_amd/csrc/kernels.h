@@ -67,7 +67,8 @@ hipError_t launch_conv(int precision, int in_mode, int epi, const ConvArgs &a, c
 int conv_block_px(int precision, int in_mode, int epi, int cout);   // pixels per work block
 // Demangled name of the kernel instantiation launch_conv would pick (as profilers list it).
 const char *conv_kernel_name(int precision, int in_mode, int epi, const ConvArgs &a);
-int conv_block_rows(int precision, int in_mode, int epi, int cout); // patch rows (cols fixed at 16)
+int conv_block_rows(int precision, int in_mode, int epi, int cout); // patch rows
+int conv_block_cols(int precision, int in_mode, int epi, int cout); // patch columns
 
 hipError_t launch_pool(int precision, const void *in, long long in_ss, void *out,
                        long long out_ss, int C, const Batch &g, hipStream_t s);

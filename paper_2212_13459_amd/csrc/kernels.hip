@@ -238,48 +238,53 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a, Batch g) {
 
 // ---------------------------------------------------------------------------------------
 // Pipelined implicit-GEMM 3x3 convolution (NHWC input) on MFMA.
-//   Work block: a 16 x 16 output patch (M = 256 pixels) x BN output channels, 4 waves in a
-//   WM x WN grid.  The K loop runs over stages (channel chunk c, filter row ky): each stage
+//   Work block: an 8 x 32 output patch (M = 256 pixels) x BN output channels, WM x WN
+//   waves.  The K loop runs over stages (channel chunk c, filter row ky): each stage
 //   stages the 3 taps of one filter row for BN channels in LDS, and the first stage of a
-//   chunk also stages the 18 x 18 halo patch of that chunk.  Stages are double-buffered:
+//   chunk also stages the 10 x 34 halo patch of that chunk.  Stages are double-buffered:
 //   the global loads of stage s+1 are in flight (in registers) while the MFMAs of stage s
 //   run, then land in the other LDS buffer; one barrier per stage.
-//   LDS rows are 64 bytes (four 16-byte chunks) with the chunk index XOR-swizzled by
-//   (row / 4) mod 4: the 16 lanes of a ds_read_b128 phase read 16 consecutive rows, and
-//   the swizzle sends them to 16 distinct 16-byte bank groups of the 64-bank LDS.
+//   A 32-row MFMA operand block is one patch row of 32 pixels, i.e. 32 consecutive LDS
+//   rows, which gfx950 reads without bank conflicts (blocks of 2 x 16 rows with a gap
+//   between them, as a 16-wide patch gives, read at half rate).  Halo-patch rows are
+//   padded to 80 bytes, so every tap and filter-row shift of an operand block is a
+//   constant byte offset (one address register per block); weight rows are 64 bytes with
+//   the 16-byte chunk index XOR-swizzled by (row / 4) mod 4, which tap shifts (multiples
+//   of BN rows) leave unchanged.
 //   Segment 1 (optional) adds the centre tap over in2 (the style residual V D~).
 // ---------------------------------------------------------------------------------------
 // Branch-free stage loads: every lane loads from a valid (clamped) address and selects
 // zero outside the window, so the compiler can track the in-flight loads exactly and
 // overlap them with the MFMAs of the current stage.
-template <typename T, int NT, int ANV, int WP, int CK, int VEC>
-__device__ __forceinline__ void stage_load_a(u32x4 (&ra)[ANV], const T *src, int cin, int c, int y0,
-                                             int x0, int h, int w, int tid) {
+// Halo-patch staging: vector v = tid + i NT covers patch row 16 (v / 64) + v % 16 and
+// 16-byte chunk (v / 16) % 4, so the 16 lanes of each LDS write phase store 16 different
+// rows of the padded layout (row stride CK + VEC elements = 80 bytes, no bank conflicts).
+// Loads are a uniform base (block origin, channel chunk) plus a 32-bit per-lane byte
+// offset; lanes outside the window load a clamped (valid) pixel and select zero.
+template <typename T, int NT, int ANV, int VEC>
+__device__ __forceinline__ void stage_load_a(u32x4 (&ra)[ANV], const T *base, const unsigned (&arel)[ANV],
+                                             const unsigned (&amask)[ANV], int cin, int apart) {
 #pragma unroll
   for (int i = 0; i < ANV; ++i) {
-    const int v = tid + i * NT;
-    const int pix = v >> 2, part = v & 3;
-    const int py = pix / WP, px = pix - py * WP;
-    const int yy = y0 - 1 + py, xx = x0 - 1 + px;
-    const bool ok = yy >= 0 && yy < h && xx >= 0 && xx < w;
-    const int cy = min(max(yy, 0), h - 1), cx = min(max(xx, 0), w - 1);
-    const u32x4 val = *(const u32x4 *)(src + ((long long)cy * w + cx) * cin + c * CK + part * VEC);
-    const unsigned m = ok ? 0xffffffffu : 0u;
-    ra[i] = val & m;
+    const unsigned off = (arel[i] * (unsigned)cin + (unsigned)(apart * VEC)) * (unsigned)sizeof(T);
+    ra[i] = *(const u32x4 *)((const char *)base + off) & amask[i];
   }
 }
 
-template <typename T, int NT, int BNV, int BN, int CK, int VEC>
-__device__ __forceinline__ void stage_load_b(u32x4 (&rb)[BNV], const T *wb, int cout_pad, int n0,
-                                             int ntap_rows, int tid) {
+template <int BNV>
+__device__ __forceinline__ void stage_load_b(u32x4 (&rb)[BNV], const void *base, const unsigned (&boff)[BNV]) {
 #pragma unroll
-  for (int i = 0; i < BNV; ++i) {
+  for (int i = 0; i < BNV; ++i) rb[i] = *(const u32x4 *)((const char *)base + boff[i]);
+}
+
+template <typename T, int NT, int ANV, int AROWS, int CK, int VEC>
+__device__ __forceinline__ void stage_store_a(T *dst, const u32x4 (&r)[ANV], int tid) {
+#pragma unroll
+  for (int i = 0; i < ANV; ++i) {
     const int v = tid + i * NT;
-    const int row = v >> 2, part = v & 3;
-    int ti = row / BN;
-    const int n = row - ti * BN;
-    ti = ti < ntap_rows ? ti : 0;            // rows past the stage's taps duplicate tap 0 (unused)
-    rb[i] = *(const u32x4 *)(wb + ((long long)ti * cout_pad + n0 + n) * CK + part * VEC);
+    const int row = (v >> 6) * 16 + (v & 15), part = (v >> 4) & 3;
+    if ((i + 1) * NT <= AROWS * 4 || row < AROWS)
+      *(u32x4 *)(&dst[row * (CK + VEC) + part * VEC]) = r[i];
   }
 }
 
@@ -296,53 +301,70 @@ __device__ __forceinline__ void stage_store(T *dst, const u32x4 (&r)[NV], int ti
   }
 }
 
-// MFMAs of one filter tap at LDS pixel offset toff.
+// One k-step of a stage: filter tap ti, channel half kh of the 64-byte LDS rows (16 BF16
+// or 4 FP32 channels per lane).  Operand fragments are one 16-byte LDS read per 32-row A
+// block and per 32-column B block.  Tap by tap, first half then second, each
+// accumulator sees the same sequence of MFMAs as a whole-row loop would give it.
+template <int TM, int TN> struct KFrag { u32x4 a[TM], b[TN]; };
+
 template <typename T, int TM, int TN, int BN, int CK, int VEC>
-__device__ __forceinline__ void tap_mma(f32x16 (&acc)[TM][TN], const T *A, const T *B,
-                                        const int (&pidx)[TM], int toff, int ti, int bcol, int half) {
-  typename Mma<T>::Frag af[TM], bfr[TN];
+__device__ __forceinline__ void load_kstep(KFrag<TM, TN> &f, const T *A, const T *B,
+                                           const int (&pidx)[TM], int toff, int ti, int kh, int bcol,
+                                           int half) {
+  const int chunk = 2 * half + kh;
 #pragma unroll
-  for (int tm = 0; tm < TM; ++tm) {
-    const int row = pidx[tm] + toff;
-    if constexpr (sizeof(T) == 2) {
-      af[tm].v[0] = *(const bf16x8 *)(&A[swz64(row, 2 * half, CK, VEC)]);
-      af[tm].v[1] = *(const bf16x8 *)(&A[swz64(row, 2 * half + 1, CK, VEC)]);
-    } else {
-      af[tm].v[0] = *(const f32x4 *)(&A[swz64(row, 2 * half, CK, VEC)]);
-      af[tm].v[1] = *(const f32x4 *)(&A[swz64(row, 2 * half + 1, CK, VEC)]);
-    }
-  }
+  for (int tm = 0; tm < TM; ++tm) f.a[tm] = *(const u32x4 *)(&A[(pidx[tm] + toff) * (CK + VEC) + chunk * VEC]);
 #pragma unroll
-  for (int tn = 0; tn < TN; ++tn) {
-    const int row = ti * BN + bcol + tn * 32;
-    if constexpr (sizeof(T) == 2) {
-      bfr[tn].v[0] = *(const bf16x8 *)(&B[swz64(row, 2 * half, CK, VEC)]);
-      bfr[tn].v[1] = *(const bf16x8 *)(&B[swz64(row, 2 * half + 1, CK, VEC)]);
-    } else {
-      bfr[tn].v[0] = *(const f32x4 *)(&B[swz64(row, 2 * half, CK, VEC)]);
-      bfr[tn].v[1] = *(const f32x4 *)(&B[swz64(row, 2 * half + 1, CK, VEC)]);
-    }
-  }
+  for (int tn = 0; tn < TN; ++tn)
+    f.b[tn] = *(const u32x4 *)(&B[swz64(ti * BN + bcol + tn * 32, chunk, CK, VEC)]);
+}
+
+template <typename T, int TM, int TN>
+__device__ __forceinline__ void mma_kstep(f32x16 (&acc)[TM][TN], const KFrag<TM, TN> &f) {
 #pragma unroll
   for (int tm = 0; tm < TM; ++tm)
 #pragma unroll
-    for (int tn = 0; tn < TN; ++tn) Mma<T>::mma(acc[tm][tn], af[tm], bfr[tn]);
+    for (int tn = 0; tn < TN; ++tn) {
+      if constexpr (sizeof(T) == 2) {
+        acc[tm][tn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, f.a[tm]),
+                                                               __builtin_bit_cast(bf16x8, f.b[tn]),
+                                                               acc[tm][tn], 0, 0, 0);
+      } else {
+        const f32x4 av = __builtin_bit_cast(f32x4, f.a[tm]), bv = __builtin_bit_cast(f32x4, f.b[tn]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[tm][tn] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[j], bv[j], acc[tm][tn], 0, 0, 0);
+      }
+    }
 }
 
-// MFMAs of one stage: NTAP taps at LDS pixel offsets toff0 + ti.  UNR unrolls the taps so
-// the fragment loads of one tap can overlap the MFMAs of the previous one (needed when a
-// SIMD runs a single wave).
-template <typename T, int TM, int TN, int BN, int CK, int VEC, int NTAP, bool UNR>
-__device__ __forceinline__ void stage_mma(f32x16 (&acc)[TM][TN], const T *A, const T *B,
-                                          const int (&pidx)[TM], int toff0, int bcol, int half) {
-  if constexpr (UNR) {
+// The MFMAs of one stage (NTAP taps at LDS pixel offsets toff0 + ti) as a software
+// pipeline over its 2 NTAP k-steps: the fragments of k-step j + 1 are read while the
+// MFMAs of k-step j run (the scheduling barrier keeps later reads from being hoisted,
+// which would cost registers).  The registers staged for the next stage (loaded by the
+// caller before this stage) are written to their LDS buffers at the second-to-last
+// k-step, so only the barrier remains at the end of the stage.
+template <typename T, int TM, int TN, int BN, int CK, int VEC, int NTAP, int NT, int ANV, int BNV,
+          int AROWS, bool SA, bool SB>
+__device__ __forceinline__ void stage_pipe(f32x16 (&acc)[TM][TN], const T *A, const T *B,
+                                           const int (&pidx)[TM], int toff0, int bcol, int half,
+                                           const u32x4 (&ra)[ANV], const u32x4 (&rb)[BNV], T *adst,
+                                           T *bdst, bool store, int tid) {
+  constexpr int NK = 2 * NTAP;
+  constexpr int JS = NK >= 2 ? NK - 2 : 0;
+  KFrag<TM, TN> f[2];
+  load_kstep<T, TM, TN, BN, CK, VEC>(f[0], A, B, pidx, toff0, 0, 0, bcol, half);
 #pragma unroll
-    for (int ti = 0; ti < NTAP; ++ti)
-      tap_mma<T, TM, TN, BN, CK, VEC>(acc, A, B, pidx, toff0 + ti, ti, bcol, half);
-  } else {
-#pragma unroll 1
-    for (int ti = 0; ti < NTAP; ++ti)
-      tap_mma<T, TM, TN, BN, CK, VEC>(acc, A, B, pidx, toff0 + ti, ti, bcol, half);
+  for (int j = 0; j < NK; ++j) {
+    if (j + 1 < NK)
+      load_kstep<T, TM, TN, BN, CK, VEC>(f[(j + 1) & 1], A, B, pidx, toff0 + (j + 1) / 2, (j + 1) / 2,
+                                         (j + 1) & 1, bcol, half);
+    mma_kstep<T, TM, TN>(acc, f[j & 1]);
+    if (j == JS && store) {
+      if constexpr (SA) stage_store_a<T, NT, ANV, AROWS, CK, VEC>(adst, ra, tid);
+      if constexpr (SB) stage_store<T, NT, BNV, CK, VEC>(bdst, rb, tid);
+    }
+    __builtin_amdgcn_sched_barrier(0);
   }
 }
 
@@ -354,9 +376,20 @@ constexpr int epi_passes(int bm, int wn, int tn, int smem_bytes) {
   return 0;
 }
 
+// Weight-row offsets of a one-tap-row stage (segment 1): rows past BN duplicate row % BN.
+template <typename T, int NT, int BNV, int BN, int CK, int VEC>
+__device__ __forceinline__ void seg_boff(unsigned (&boff)[BNV], int cout_pad, int n0, int tid) {
+  (void)cout_pad;
+#pragma unroll
+  for (int i = 0; i < BNV; ++i) {
+    const int n = ((tid + i * NT) >> 2) % BN;
+    boff[i] = (unsigned)(((n0 + n) * CK + (tid & 3) * VEC) * (int)sizeof(T));
+  }
+}
+
 template <typename T, int BN, int WM, int WN, int EPI, bool SEG2>
 __global__ __launch_bounds__(WM * WN * 64) void k_conv2(ConvArgs a, Batch g) {
-  constexpr int PH = 16, PW = 16, BM = PH * PW;
+  constexpr int PH = 8, PW = 32, BM = PH * PW;
   constexpr int NT = WM * WN * 64;
   constexpr int TM = BM / (WM * 32), TN = BN / (WN * 32);
   static_assert(TM >= 1 && TN >= 1 && TM * WM * 32 == BM && TN * WN * 32 == BN, "bad wave tiling");
@@ -367,13 +400,11 @@ __global__ __launch_bounds__(WM * WN * 64) void k_conv2(ConvArgs a, Batch g) {
   constexpr int BROWS = 3 * BN;
   constexpr int ANV = (AROWS * 4 + NT - 1) / NT;
   constexpr int BNV = (BROWS * 4 + NT - 1) / NT;
-  constexpr int AROWS_P = ANV * NT / 4;         // padded so every thread's store lands in the buffer
   constexpr int BROWS_P = BNV * NT / 4;
-  constexpr int ASZ = AROWS_P * CK, BSZ = BROWS_P * CK;
+  constexpr int ASZ = AROWS * (CK + VEC), BSZ = BROWS_P * CK;
   static_assert(epi_passes(BM, WN, TN, 2 * (ASZ + BSZ) * (int)sizeof(T)) > 0, "epilogue does not fit");
   // wide wave tiles (one wave per SIMD): accumulators in AGPRs, taps unrolled
   constexpr bool WIDE = TM * TN >= 16;
-  constexpr bool UNRT = false;
   __shared__ __attribute__((aligned(16))) T sm[2 * (ASZ + BSZ)];
   if constexpr (WIDE) asm volatile("" ::: "a0");
 
@@ -411,60 +442,88 @@ __global__ __launch_bounds__(WM * WN * 64) void k_conv2(ConvArgs a, Batch g) {
   const int nck2 = SEG2 ? a.cin2 / CK : 0;
   u32x4 ra[ANV], rb[BNV];
 
-  // stage (c, ky) of segment 0 uses A buffer c & 1 and B buffer (3 c + ky) & 1; segment-1
-  // chunk c2 is stage 3 nck + c2 with A buffer (nck + c2) & 1.
-  stage_load_a<T, NT, ANV, WP, CK, VEC>(ra, in0, a.cin, 0, y0, x0, h, w, tid);
-  stage_load_b<T, NT, BNV, BN, CK, VEC>(rb, wp0, a.cout_pad, n0, 3, tid);
-  stage_store<T, NT, ANV, CK, VEC>((sm + ASZ * (0)), ra, tid);
-  stage_store<T, NT, BNV, CK, VEC>((sm + 2 * ASZ + BSZ * (0)), rb, tid);
+  // per-lane staging offsets, computed once: halo pixel relative to the block's clamped
+  // origin (by, bx) and its in-window mask; weight row (tap row ti < 3, channel n) offsets
+  const int by = max(y0 - 1, 0), bx = max(x0 - 1, 0);
+  const int apart = (tid >> 4) & 3;
+  unsigned arel[ANV], amask[ANV], boff[BNV];
+#pragma unroll
+  for (int i = 0; i < ANV; ++i) {
+    const int v = tid + i * NT;
+    const int pix = (v >> 6) * 16 + (v & 15);
+    const int py = pix / WP, px = pix - py * WP;
+    const int yy = y0 - 1 + py, xx = x0 - 1 + px;
+    const int cy = min(max(yy, 0), h - 1), cx = min(max(xx, 0), w - 1);
+    arel[i] = (unsigned)((cy - by) * w + (cx - bx));
+    amask[i] = (yy >= 0 && yy < h && xx >= 0 && xx < w) ? 0xffffffffu : 0u;
+  }
+#pragma unroll
+  for (int i = 0; i < BNV; ++i) {
+    const int row = (tid + i * NT) >> 2;
+    int ti = row / BN;
+    const int n = row - ti * BN;
+    ti = ti < 3 ? ti : 0;                    // rows past the stage's taps duplicate tap 0 (unused)
+    boff[i] = (unsigned)(((ti * a.cout_pad + n0 + n) * CK + (tid & 3) * VEC) * (int)sizeof(T));
+  }
+  const T *abase0 = in0 + ((long long)by * w + bx) * a.cin;
+  const long long wrow = (long long)a.cout_pad * CK;   // elements per filter tap of a chunk
+
+  // stage (c, ky) of segment 0 uses A buffer c & 1 and B buffer (3 c + ky) & 1
+  stage_load_a<T, NT, ANV, VEC>(ra, abase0, arel, amask, a.cin, apart);
+  stage_load_b<BNV>(rb, wp0, boff);
+  stage_store_a<T, NT, ANV, AROWS, CK, VEC>(sm, ra, tid);
+  stage_store<T, NT, BNV, CK, VEC>(sm + 2 * ASZ, rb, tid);
   __syncthreads();
+  T *const A0 = sm, *const A1 = sm + ASZ, *const B0 = sm + 2 * ASZ, *const B1 = sm + 2 * ASZ + BSZ;
+  const int bcol = wn * TN * 32 + l32;
 #pragma unroll 1
   for (int c = 0; c < nck; ++c) {
-    const int ab = c & 1, s0 = 3 * c;
-    // filter row 0; prefetch row 1 (weights only)
-    stage_load_b<T, NT, BNV, BN, CK, VEC>(rb, wp0 + ((long long)c * 9 + 3) * a.cout_pad * CK,
-                                          a.cout_pad, n0, 3, tid);
-    stage_mma<T, TM, TN, BN, CK, VEC, 3, UNRT>(acc, (sm + ASZ * (ab)), (sm + 2 * ASZ + BSZ * (s0 & 1)), pidx, 0, wn * TN * 32 + l32, half);
-    stage_store<T, NT, BNV, CK, VEC>((sm + 2 * ASZ + BSZ * ((s0 + 1) & 1)), rb, tid);
+    const bool odd = c & 1;
+    T *const Ac = odd ? A1 : A0, *const An = odd ? A0 : A1;
+    // stage index 3 c + ky selects the B buffer; 3 c is odd when c is
+    T *const Bx = odd ? B1 : B0, *const By = odd ? B0 : B1;
+    // filter row 0 (B buffer x); prefetch row 1 into y
+    stage_load_b<BNV>(rb, wp0 + (c * 9 + 3) * wrow, boff);
+    stage_pipe<T, TM, TN, BN, CK, VEC, 3, NT, ANV, BNV, AROWS, false, true>(acc, Ac, Bx, pidx, 0, bcol, half, ra,
+                                                                          rb, nullptr, By, true, tid);
     __syncthreads();
-    // filter row 1; prefetch row 2
-    stage_load_b<T, NT, BNV, BN, CK, VEC>(rb, wp0 + ((long long)c * 9 + 6) * a.cout_pad * CK,
-                                          a.cout_pad, n0, 3, tid);
-    stage_mma<T, TM, TN, BN, CK, VEC, 3, UNRT>(acc, (sm + ASZ * (ab)), (sm + 2 * ASZ + BSZ * ((s0 + 1) & 1)), pidx, WP, wn * TN * 32 + l32, half);
-    stage_store<T, NT, BNV, CK, VEC>((sm + 2 * ASZ + BSZ * ((s0 + 2) & 1)), rb, tid);
+    // filter row 1 (y); prefetch row 2 into x
+    stage_load_b<BNV>(rb, wp0 + (c * 9 + 6) * wrow, boff);
+    stage_pipe<T, TM, TN, BN, CK, VEC, 3, NT, ANV, BNV, AROWS, false, true>(acc, Ac, By, pidx, WP, bcol, half, ra,
+                                                                          rb, nullptr, Bx, true, tid);
     __syncthreads();
-    // filter row 2; prefetch the next chunk's halo patch and row 0 (or segment 1)
+    // filter row 2 (x); prefetch the next chunk's halo patch and row 0 (or segment 1) into
+    // the other A buffer and y
     const bool more = c + 1 < nck;
+    const bool seg = !more && SEG2 && nck2 > 0;
     if (more) {
-      stage_load_a<T, NT, ANV, WP, CK, VEC>(ra, in0, a.cin, c + 1, y0, x0, h, w, tid);
-      stage_load_b<T, NT, BNV, BN, CK, VEC>(rb, wp0 + (long long)(c + 1) * 9 * a.cout_pad * CK,
-                                            a.cout_pad, n0, 3, tid);
-    } else if (SEG2 && nck2 > 0) {
-      stage_load_a<T, NT, ANV, WP, CK, VEC>(ra, in1, a.cin2, 0, y0, x0, h, w, tid);
-      stage_load_b<T, NT, BNV, BN, CK, VEC>(rb, wp1, a.cout_pad, n0, 1, tid);
+      stage_load_a<T, NT, ANV, VEC>(ra, abase0 + (c + 1) * CK, arel, amask, a.cin, apart);
+      stage_load_b<BNV>(rb, wp0 + (c + 1) * 9 * wrow, boff);
+    } else if (seg) {
+      const T *abase1 = in1 + ((long long)by * w + bx) * a.cin2;
+      stage_load_a<T, NT, ANV, VEC>(ra, abase1, arel, amask, a.cin2, apart);
+      seg_boff<T, NT, BNV, BN, CK, VEC>(boff, a.cout_pad, n0, tid);
+      stage_load_b<BNV>(rb, wp1, boff);
     }
-    stage_mma<T, TM, TN, BN, CK, VEC, 3, UNRT>(acc, (sm + ASZ * (ab)), (sm + 2 * ASZ + BSZ * ((s0 + 2) & 1)), pidx, 2 * WP, wn * TN * 32 + l32, half);
-    if (more || (SEG2 && nck2 > 0)) {
-      stage_store<T, NT, ANV, CK, VEC>((sm + ASZ * ((c + 1) & 1)), ra, tid);
-      stage_store<T, NT, BNV, CK, VEC>((sm + 2 * ASZ + BSZ * ((s0 + 3) & 1)), rb, tid);
-    }
+    stage_pipe<T, TM, TN, BN, CK, VEC, 3, NT, ANV, BNV, AROWS, true, true>(acc, Ac, Bx, pidx, 2 * WP, bcol, half,
+                                                                         ra, rb, An, By, more || seg, tid);
     __syncthreads();
   }
   if constexpr (SEG2) {
+    // segment-1 chunk c2 is stage 3 nck + c2 with A buffer (nck + c2) & 1; boff now holds
+    // the one-tap-row weight offsets
+    const T *abase1 = in1 + ((long long)by * w + bx) * a.cin2;
 #pragma unroll 1
     for (int c2 = 0; c2 < nck2; ++c2) {
       const int st = 3 * nck + c2, ac = nck + c2;
       const bool more = c2 + 1 < nck2;
       if (more) {
-        stage_load_a<T, NT, ANV, WP, CK, VEC>(ra, in1, a.cin2, c2 + 1, y0, x0, h, w, tid);
-        stage_load_b<T, NT, BNV, BN, CK, VEC>(rb, wp1 + (long long)(c2 + 1) * a.cout_pad * CK,
-                                              a.cout_pad, n0, 1, tid);
+        stage_load_a<T, NT, ANV, VEC>(ra, abase1 + (c2 + 1) * CK, arel, amask, a.cin2, apart);
+        stage_load_b<BNV>(rb, wp1 + (long long)(c2 + 1) * wrow, boff);
       }
-      stage_mma<T, TM, TN, BN, CK, VEC, 1, UNRT>(acc, (sm + ASZ * (ac & 1)), (sm + 2 * ASZ + BSZ * (st & 1)), pidx, WP + 1, wn * TN * 32 + l32, half);
-      if (more) {
-        stage_store<T, NT, ANV, CK, VEC>((sm + ASZ * ((ac + 1) & 1)), ra, tid);
-        stage_store<T, NT, BNV, CK, VEC>((sm + 2 * ASZ + BSZ * ((st + 1) & 1)), rb, tid);
-      }
+      stage_pipe<T, TM, TN, BN, CK, VEC, 1, NT, ANV, BNV, AROWS, true, true>(
+          acc, (ac & 1) ? A1 : A0, (st & 1) ? B1 : B0, pidx, WP + 1, bcol, half, ra, rb,
+          (ac & 1) ? A0 : A1, (st & 1) ? B0 : B1, more, tid);
       __syncthreads();
     }
   }
@@ -683,11 +742,15 @@ static hipError_t run_conv(const ConvArgs &a, const Batch &g, hipStream_t s) {
 int conv_block_rows(int precision, int in_mode, int epi, int cout) {
   (void)precision;
   if (epi == EPI_STITCH) return 8;
-  if (in_mode == IN_NHWC) return 16;    // k_conv2
+  if (in_mode == IN_NHWC) return 8;     // k_conv2
   return cout <= 64 ? 16 : 8;
 }
+int conv_block_cols(int precision, int in_mode, int epi, int cout) {
+  (void)precision; (void)cout;
+  return (in_mode == IN_NHWC && epi != EPI_STITCH) ? 32 : 16;
+}
 int conv_block_px(int precision, int in_mode, int epi, int cout) {
-  return 16 * conv_block_rows(precision, in_mode, epi, cout);
+  return conv_block_cols(precision, in_mode, epi, cout) * conv_block_rows(precision, in_mode, epi, cout);
 }
 int ck_of(int precision) { return precision == 1 ? Tr<bf16>::CK : Tr<float>::CK; }
 size_t elem_size(int precision) { return precision == 1 ? 2 : 4; }

@@ -586,9 +586,10 @@ struct Runner {
   }
   void conv_pfx(Batch &b, int in_mode, int epi, int cout) const {
     const int ph = conv_block_rows(c->prec, in_mode, epi, cout);
+    const int pw = conv_block_cols(c->prec, in_mode, epi, cout);
     b.pfx[0] = 0;
     for (int k = 0; k < b.n; ++k)
-      b.pfx[k + 1] = b.pfx[k] + ((b.h[k] + ph - 1) / ph) * ((b.w[k] + 15) / 16);
+      b.pfx[k + 1] = b.pfx[k] + ((b.h[k] + ph - 1) / ph) * ((b.w[k] + pw - 1) / pw);
   }
   void items_pfx(Batch &b, const std::vector<long long> &items, int per_block) const {
     b.pfx[0] = 0;
