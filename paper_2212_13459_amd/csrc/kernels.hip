@@ -387,9 +387,100 @@ __device__ __forceinline__ void seg_boff(unsigned (&boff)[BNV], int cout_pad, in
   }
 }
 
-template <typename T, int BN, int WM, int WN, int EPI, bool SEG2>
+// Conv epilogue through LDS (the caller's last barrier has released its stage buffers,
+// SMEM_BYTES of them at sm), in NPASS passes over the wave's TN column blocks: phase 1
+// writes the raw FP32 accumulators of the pass, phase 2 reads VEC consecutive channels of
+// one pixel and applies bias + ReLU (+ content difference) or content residual + ReLU
+// mask with 16-byte loads and stores.  The arithmetic per element is the same as
+// applying it to the accumulator directly.
+template <typename T, int BN, int WM, int WN, int PH, int EPI, int SMEM_BYTES>
+__device__ __forceinline__ void conv_epilogue(f32x16 (&acc)[PH * 32 / (WM * 32)][BN / (WN * 32)], T *sm,
+                                              const ConvArgs &a, const Batch &g, int t, long long slot,
+                                              int y0, int x0, int h, int w, int n0, int tid, int wm, int wn,
+                                              int l32, int half) {
+  constexpr int PW = 32, BM = PH * PW, NT = WM * WN * 64;
+  constexpr int TM = BM / (WM * 32), TN = BN / (WN * 32);
+  constexpr int VEC = 16 / sizeof(T);
+  constexpr int NPASS = epi_passes(BM, WN, TN, SMEM_BYTES);
+  constexpr int TNP = TN / NPASS, CW = TNP * 32, RSW = WN * CW + 8;
+  constexpr int CPR = WN * CW / VEC;
+  static_assert((BM * CPR) % NT == 0, "epilogue tiling");
+  typedef T TV __attribute__((ext_vector_type(VEC)));
+  float *so = (float *)sm;
+  const int cout = a.cout;
+#pragma unroll
+  for (int p = 0; p < NPASS; ++p) {
+    if (p > 0) __syncthreads();
+#pragma unroll
+    for (int tm = 0; tm < TM; ++tm)
+#pragma unroll
+      for (int tq = 0; tq < TNP; ++tq)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int m = wm * TM * 32 + tm * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+          so[m * RSW + wn * CW + tq * 32 + l32] = acc[tm][p * TNP + tq][r];
+        }
+    __syncthreads();
+#pragma unroll 2
+    for (int i = 0; i < BM * CPR / NT; ++i) {
+      const int idx = tid + i * NT;
+      const int m = idx / CPR, lc = (idx % CPR) * VEC;
+      const int n = n0 + (lc / CW) * TN * 32 + p * CW + lc % CW;
+      const int py = y0 + m / PW, px = x0 + m % PW;
+      if (py >= h || px >= w || n >= cout) continue;
+      const long long pix = (long long)py * w + px;
+      float v[VEC];
+#pragma unroll
+      for (int q = 0; q < VEC / 4; ++q) {
+        const f32x4 u = *(const f32x4 *)(&so[m * RSW + lc + 4 * q]);
+        v[4 * q] = u[0]; v[4 * q + 1] = u[1]; v[4 * q + 2] = u[2]; v[4 * q + 3] = u[3];
+      }
+      if (EPI == EPI_FWD) {
+#pragma unroll
+        for (int q = 0; q < VEC / 4; ++q) {
+          const f32x4 b = *(const f32x4 *)(a.bias + n + 4 * q);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) v[4 * q + e] = fmaxf(v[4 * q + e] + b[e], 0.f);
+        }
+        if (a.rc) {
+          const float *f = a.fc + ((long long)(g.gy[t] + py) * a.fc_w + (g.gx[t] + px)) * cout + n;
+          float *rc = a.rc + slot * a.rc_ss + pix * cout + n;
+#pragma unroll
+          for (int q = 0; q < VEC / 4; ++q) {
+            f32x4 d;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) d[e] = v[4 * q + e] - f[4 * q + e];
+            *(f32x4 *)(rc + 4 * q) = d;
+          }
+        }
+      } else {
+        if (a.rc) {
+          const float *rc = a.rc + slot * a.rc_ss + pix * cout + n;
+#pragma unroll
+          for (int q = 0; q < VEC / 4; ++q) {
+            const f32x4 d = *(const f32x4 *)(rc + 4 * q);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) v[4 * q + e] += a.two_alpha * d[e];
+          }
+        }
+        if (a.mask) {
+          const TV mk = *(const TV *)((const T *)a.mask + slot * a.mask_ss + pix * cout + n);
+#pragma unroll
+          for (int e = 0; e < VEC; ++e)
+            if (!(to_f(mk[e]) > 0.f)) v[e] = 0.f;
+        }
+      }
+      TV o;
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) o[e] = from_f<T>(v[e]);
+      *(TV *)((T *)a.out + slot * a.out_ss + pix * cout + n) = o;
+    }
+  }
+}
+
+template <typename T, int BN, int WM, int WN, int PH, int EPI, bool SEG2>
 __global__ __launch_bounds__(WM * WN * 64) void k_conv2(ConvArgs a, Batch g) {
-  constexpr int PH = 8, PW = 32, BM = PH * PW;
+  constexpr int PW = 32, BM = PH * PW;
   constexpr int NT = WM * WN * 64;
   constexpr int TM = BM / (WM * 32), TN = BN / (WN * 32);
   static_assert(TM >= 1 && TN >= 1 && TM * WM * 32 == BM && TN * WN * 32 == BN, "bad wave tiling");
@@ -528,95 +619,224 @@ __global__ __launch_bounds__(WM * WN * 64) void k_conv2(ConvArgs a, Batch g) {
     }
   }
 
-  // Epilogue through LDS (the last stage barrier has released the stage buffers), in
-  // NPASS passes over the wave's TN column blocks: phase 1 writes the raw FP32
-  // accumulators of the pass, phase 2 reads VEC consecutive channels of one pixel and
-  // applies bias + ReLU (+ content difference) or content residual + ReLU mask with
-  // 16-byte loads and stores.  The arithmetic per element is the same as applying it to
-  // the accumulator directly.
-  constexpr int NPASS = epi_passes(BM, WN, TN, 2 * (ASZ + BSZ) * (int)sizeof(T));
-  constexpr int TNP = TN / NPASS, CW = TNP * 32, RSW = WN * CW + 8;
-  constexpr int CPR = WN * CW / VEC;
-  static_assert((BM * CPR) % NT == 0, "epilogue tiling");
-  typedef T TV __attribute__((ext_vector_type(VEC)));
-  float *so = (float *)sm;
-  const int cout = a.cout;
-#pragma unroll
-  for (int p = 0; p < NPASS; ++p) {
-    if (p > 0) __syncthreads();
-#pragma unroll
-    for (int tm = 0; tm < TM; ++tm)
-#pragma unroll
-      for (int tq = 0; tq < TNP; ++tq)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int m = wm * TM * 32 + tm * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
-          so[m * RSW + wn * CW + tq * 32 + l32] = acc[tm][p * TNP + tq][r];
-        }
-    __syncthreads();
-#pragma unroll 2
-    for (int i = 0; i < BM * CPR / NT; ++i) {
-      const int idx = tid + i * NT;
-      const int m = idx / CPR, lc = (idx % CPR) * VEC;
-      const int n = n0 + (lc / CW) * TN * 32 + p * CW + lc % CW;
-      const int py = y0 + m / PW, px = x0 + m % PW;
-      if (py >= h || px >= w || n >= cout) continue;
-      const long long pix = (long long)py * w + px;
-      float v[VEC];
-#pragma unroll
-      for (int q = 0; q < VEC / 4; ++q) {
-        const f32x4 u = *(const f32x4 *)(&so[m * RSW + lc + 4 * q]);
-        v[4 * q] = u[0]; v[4 * q + 1] = u[1]; v[4 * q + 2] = u[2]; v[4 * q + 3] = u[3];
-      }
-      if (EPI == EPI_FWD) {
-#pragma unroll
-        for (int q = 0; q < VEC / 4; ++q) {
-          const f32x4 b = *(const f32x4 *)(a.bias + n + 4 * q);
-#pragma unroll
-          for (int e = 0; e < 4; ++e) v[4 * q + e] = fmaxf(v[4 * q + e] + b[e], 0.f);
-        }
-        if (a.rc) {
-          const float *f = a.fc + ((long long)(g.gy[t] + py) * a.fc_w + (g.gx[t] + px)) * cout + n;
-          float *rc = a.rc + slot * a.rc_ss + pix * cout + n;
-#pragma unroll
-          for (int q = 0; q < VEC / 4; ++q) {
-            f32x4 d;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) d[e] = v[4 * q + e] - f[4 * q + e];
-            *(f32x4 *)(rc + 4 * q) = d;
-          }
-        }
-      } else {
-        if (a.rc) {
-          const float *rc = a.rc + slot * a.rc_ss + pix * cout + n;
-#pragma unroll
-          for (int q = 0; q < VEC / 4; ++q) {
-            const f32x4 d = *(const f32x4 *)(rc + 4 * q);
-#pragma unroll
-            for (int e = 0; e < 4; ++e) v[4 * q + e] += a.two_alpha * d[e];
-          }
-        }
-        if (a.mask) {
-          const TV mk = *(const TV *)((const T *)a.mask + slot * a.mask_ss + pix * cout + n);
-#pragma unroll
-          for (int e = 0; e < VEC; ++e)
-            if (!(to_f(mk[e]) > 0.f)) v[e] = 0.f;
-        }
-      }
-      TV o;
-#pragma unroll
-      for (int e = 0; e < VEC; ++e) o[e] = from_f<T>(v[e]);
-      *(TV *)((T *)a.out + slot * a.out_ss + pix * cout + n) = o;
-    }
-  }
+  conv_epilogue<T, BN, WM, WN, PH, EPI, 2 * (ASZ + BSZ) * (int)sizeof(T)>(acc, sm, a, g, t, slot, y0, x0, h, w,
+                                                                        n0, tid, wm, wn, l32, half);
 }
 
-template <typename T, int BN, int WM, int WN, int EPI, bool SEG2>
+template <typename T, int BN, int WM, int WN, int PH, int EPI, bool SEG2>
 static hipError_t run_conv2(const ConvArgs &a, const Batch &g, hipStream_t s) {
   const int nblk = g.pfx[g.n];
   if (nblk == 0) return hipSuccess;
   dim3 grid(nblk, (a.cout + BN - 1) / BN);
-  hipLaunchKernelGGL((k_conv2<T, BN, WM, WN, EPI, SEG2>), grid, dim3(WM * WN * 64), 0, s, a, g);
+  hipLaunchKernelGGL((k_conv2<T, BN, WM, WN, PH, EPI, SEG2>), grid, dim3(WM * WN * 64), 0, s, a, g);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------
+// The same convolution with its stages filled by LDS DMA (global_load_lds_dwordx4): each
+// lane's 16 bytes go straight to LDS at the wave's base + 16 x lane, so no registers hold
+// staged data and no LDS store instructions are issued; the next stage's loads are in
+// flight during the whole current stage, and a stage ends with a wait for this wave's
+// loads and the barrier.  Layouts are those of k_conv2: the halo patch in 80-byte rows
+// (unit p of a chunk is row p / 5, 16-byte chunk p % 5; chunk 4 is padding), weights in
+// 64-byte rows with the chunk XOR-swizzled by (row / 4) mod 4, applied on the global side.
+// Halo positions outside the window and padding units read a zero row.
+// ---------------------------------------------------------------------------------------
+__device__ __attribute__((aligned(16))) unsigned kZeroRow[4] = {0u, 0u, 0u, 0u};
+
+typedef __attribute__((address_space(3))) void lds_void;
+
+template <typename T, int NT, int ANVD, int AUNITS, int VEC>
+__device__ __forceinline__ void dma_a(T *__restrict__ dst, const T *base, const unsigned (&arel)[ANVD],
+                                      unsigned okbits, int cin, int wv, int tid) {
+#pragma unroll
+  for (int i = 0; i < ANVD; ++i) {
+    if (i * NT + wv * 64 >= AUNITS) break;   // the wave's 64 units lie past the patch
+    const unsigned unit = (unsigned)((i * NT + tid) % 5);
+    const unsigned off = (arel[i] * (unsigned)cin + unit * VEC) * (unsigned)sizeof(T);
+    const void *gp = ((okbits >> i) & 1u) ? (const void *)((const char *)base + off) : (const void *)kZeroRow;
+    __builtin_amdgcn_global_load_lds(gp, (lds_void *)(dst + (i * NT + wv * 64) * VEC), 16, 0, 0);
+  }
+}
+
+template <typename T, int NT, int BNV, int VEC>
+__device__ __forceinline__ void dma_b(T *__restrict__ dst, const T *wbase, const unsigned (&boff)[BNV],
+                                      int wv) {
+#pragma unroll
+  for (int i = 0; i < BNV; ++i)
+    __builtin_amdgcn_global_load_lds((const void *)((const char *)wbase + boff[i]),
+                                     (lds_void *)(dst + (i * NT + wv * 64) * VEC), 16, 0, 0);
+}
+
+// Weight-row offsets with the LDS swizzle on the global side: unit p = i NT + tid of a
+// stage is weight row p / 4 (tap row ti < NROWS, channel n), physical chunk p % 4, which
+// holds logical chunk (p % 4) ^ ((row / 4) mod 4).  Rows past the stage's taps repeat tap 0.
+template <typename T, int NT, int BNV, int BN, int CK, int VEC>
+__device__ __forceinline__ void dma_boff(unsigned (&boff)[BNV], int nrows, int cout_pad, int n0, int tid) {
+#pragma unroll
+  for (int i = 0; i < BNV; ++i) {
+    const int row = (i * NT + tid) >> 2;
+    int ti = row / BN;
+    const int n = row - ti * BN;
+    ti = ti < nrows ? ti : 0;
+    const int lchunk = (tid & 3) ^ ((row >> 2) & 3);
+    boff[i] = (unsigned)(((ti * cout_pad + n0 + n) * CK + lchunk * VEC) * (int)sizeof(T));
+  }
+}
+
+// One stage: issue the next stage's DMA (if any), then the k-step pipeline over this
+// stage's buffers, then wait for this wave's DMA (the caller's barrier follows).
+template <typename T, int TM, int TN, int BN, int CK, int VEC, int NTAP, int NT, int ANVD, int AUNITS, int BNV,
+          bool DA, bool DB>
+__device__ __forceinline__ void stage_dma(f32x16 (&acc)[TM][TN], const T *__restrict__ A,
+                                          const T *__restrict__ B, const int (&pidx)[TM], int toff0, int bcol,
+                                          int half, T *__restrict__ adst, const T *abase,
+                                          const unsigned (&arel)[ANVD], unsigned okbits, int cin,
+                                          T *__restrict__ bdst, const T *wbase, const unsigned (&boff)[BNV],
+                                          bool issue, int wv, int tid) {
+  if (issue) {
+    if constexpr (DA) dma_a<T, NT, ANVD, AUNITS, VEC>(adst, abase, arel, okbits, cin, wv, tid);
+    if constexpr (DB) dma_b<T, NT, BNV, VEC>(bdst, wbase, boff, wv);
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  constexpr int NK = 2 * NTAP;
+  KFrag<TM, TN> f[2];
+  load_kstep<T, TM, TN, BN, CK, VEC>(f[0], A, B, pidx, toff0, 0, 0, bcol, half);
+#pragma unroll
+  for (int j = 0; j < NK; ++j) {
+    if (j + 1 < NK)
+      load_kstep<T, TM, TN, BN, CK, VEC>(f[(j + 1) & 1], A, B, pidx, toff0 + (j + 1) / 2, (j + 1) / 2,
+                                         (j + 1) & 1, bcol, half);
+    mma_kstep<T, TM, TN>(acc, f[j & 1]);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+}
+
+template <typename T, int BN, int WM, int WN, int PH, int EPI, bool SEG2>
+__global__ __launch_bounds__(WM * WN * 64) void k_conv3(ConvArgs a, Batch g) {
+  constexpr int PW = 32, BM = PH * PW;
+  constexpr int NT = WM * WN * 64;
+  constexpr int TM = BM / (WM * 32), TN = BN / (WN * 32);
+  static_assert(TM >= 1 && TN >= 1 && TM * WM * 32 == BM && TN * WN * 32 == BN, "bad wave tiling");
+  constexpr int CK = Tr<T>::CK;
+  constexpr int VEC = 16 / sizeof(T);
+  constexpr int HP = PH + 2, WP = PW + 2;
+  constexpr int AROWS = HP * WP;
+  constexpr int ANVD = (AROWS * 5 + NT - 1) / NT;   // 16-byte units per thread per halo chunk
+  constexpr int AUNITS = (AROWS * 5 + 63) / 64 * 64;  // units written (whole waves)
+  constexpr int BNV = (3 * BN * 4 + NT - 1) / NT;
+  constexpr int ASZ = AUNITS * VEC, BSZ = BNV * NT * VEC;
+  static_assert(ANVD <= 32, "halo mask bits");
+  static_assert(epi_passes(BM, WN, TN, 2 * (ASZ + BSZ) * (int)sizeof(T)) > 0, "epilogue does not fit");
+  constexpr bool WIDE = TM * TN >= 16;
+  __shared__ __attribute__((aligned(16))) T sm[2 * (ASZ + BSZ)];
+  if constexpr (WIDE) asm volatile("" ::: "a0");
+
+  const int t = find_tile(g, blockIdx.x);
+  const int lb = blockIdx.x - g.pfx[t];
+  const int h = g.h[t], w = g.w[t];
+  const int nbx = (w + PW - 1) / PW;
+  const int y0 = (lb / nbx) * PH, x0 = (lb % nbx) * PW;
+  const int n0 = blockIdx.y * BN;
+  const long long slot = g.slot[t];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = wv / WN, wn = wv % WN;
+  const int l32 = lane & 31, half = lane >> 5;
+
+  int pidx[TM];
+#pragma unroll
+  for (int tm = 0; tm < TM; ++tm) {
+    const int m = wm * TM * 32 + tm * 32 + l32;
+    pidx[tm] = (m / PW) * WP + (m % PW);
+  }
+  f32x16 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+  const T *in0 = (const T *)a.in + slot * a.in_ss;
+  const T *in1 = SEG2 ? (const T *)a.in2 + slot * a.in2_ss : nullptr;
+  const T *wp0 = (const T *)a.wp;
+  const T *wp1 = (const T *)a.wp2;
+  const int nck = a.cin / CK;
+  const int nck2 = SEG2 ? a.cin2 / CK : 0;
+
+  // per-lane DMA sources, computed once: halo pixel relative to the block's clamped origin
+  // (by, bx) with a valid bit (inside the window, a data unit, inside the patch)
+  const int by = max(y0 - 1, 0), bx = max(x0 - 1, 0);
+  unsigned arel[ANVD], okbits = 0u, boff[BNV];
+#pragma unroll
+  for (int i = 0; i < ANVD; ++i) {
+    const int p = i * NT + tid;
+    const int row = p / 5, unit = p - row * 5;
+    const int py = row / WP, px = row - py * WP;
+    const int yy = y0 - 1 + py, xx = x0 - 1 + px;
+    const int cy = min(max(yy, 0), h - 1), cx = min(max(xx, 0), w - 1);
+    arel[i] = (unsigned)((cy - by) * w + (cx - bx));
+    const bool ok = row < AROWS && unit < 4 && yy >= 0 && yy < h && xx >= 0 && xx < w;
+    okbits |= (ok ? 1u : 0u) << i;
+  }
+  dma_boff<T, NT, BNV, BN, CK, VEC>(boff, 3, a.cout_pad, n0, tid);
+  const T *abase0 = in0 + ((long long)by * w + bx) * a.cin;
+  const long long wrow = (long long)a.cout_pad * CK;
+
+  T *const A0 = sm, *const A1 = sm + ASZ, *const B0 = sm + 2 * ASZ, *const B1 = sm + 2 * ASZ + BSZ;
+  dma_a<T, NT, ANVD, AUNITS, VEC>(A0, abase0, arel, okbits, a.cin, wv, tid);
+  dma_b<T, NT, BNV, VEC>(B0, wp0, boff, wv);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  const int bcol = wn * TN * 32 + l32;
+#pragma unroll 1
+  for (int c = 0; c < nck; ++c) {
+    const bool odd = c & 1;
+    T *const Ac = odd ? A1 : A0, *const An = odd ? A0 : A1;
+    T *const Bx = odd ? B1 : B0, *const By = odd ? B0 : B1;
+    stage_dma<T, TM, TN, BN, CK, VEC, 3, NT, ANVD, AUNITS, BNV, false, true>(
+        acc, Ac, Bx, pidx, 0, bcol, half, nullptr, nullptr, arel, okbits, 0, By, wp0 + (c * 9 + 3) * wrow, boff,
+        true, wv, tid);
+    __syncthreads();
+    stage_dma<T, TM, TN, BN, CK, VEC, 3, NT, ANVD, AUNITS, BNV, false, true>(
+        acc, Ac, By, pidx, WP, bcol, half, nullptr, nullptr, arel, okbits, 0, Bx, wp0 + (c * 9 + 6) * wrow, boff,
+        true, wv, tid);
+    __syncthreads();
+    const bool more = c + 1 < nck;
+    const bool seg = !more && SEG2 && nck2 > 0;
+    if (seg) dma_boff<T, NT, BNV, BN, CK, VEC>(boff, 1, a.cout_pad, n0, tid);
+    const T *anext = more ? abase0 + (c + 1) * CK : (SEG2 ? in1 + ((long long)by * w + bx) * a.cin2 : abase0);
+    const T *wnext = more ? wp0 + (c + 1) * 9 * wrow : wp1;
+    stage_dma<T, TM, TN, BN, CK, VEC, 3, NT, ANVD, AUNITS, BNV, true, true>(
+        acc, Ac, Bx, pidx, 2 * WP, bcol, half, An, anext, arel, okbits, more ? a.cin : a.cin2, By, wnext, boff,
+        more || seg, wv, tid);
+    __syncthreads();
+  }
+  if constexpr (SEG2) {
+    const T *abase1 = in1 + ((long long)by * w + bx) * a.cin2;
+#pragma unroll 1
+    for (int c2 = 0; c2 < nck2; ++c2) {
+      const int st = 3 * nck + c2, ac = nck + c2;
+      const bool more = c2 + 1 < nck2;
+      stage_dma<T, TM, TN, BN, CK, VEC, 1, NT, ANVD, AUNITS, BNV, true, true>(
+          acc, (ac & 1) ? A1 : A0, (st & 1) ? B1 : B0, pidx, WP + 1, bcol, half, (ac & 1) ? A0 : A1,
+          abase1 + (c2 + 1) * CK, arel, okbits, a.cin2, (st & 1) ? B0 : B1, wp1 + (long long)(c2 + 1) * wrow,
+          boff, more, wv, tid);
+      __syncthreads();
+    }
+  }
+  conv_epilogue<T, BN, WM, WN, PH, EPI, 2 * (ASZ + BSZ) * (int)sizeof(T)>(acc, sm, a, g, t, slot, y0, x0, h, w,
+                                                                        n0, tid, wm, wn, l32, half);
+}
+
+template <typename T, int BN, int WM, int WN, int PH, int EPI, bool SEG2>
+static hipError_t run_conv3(const ConvArgs &a, const Batch &g, hipStream_t s) {
+  const int nblk = g.pfx[g.n];
+  if (nblk == 0) return hipSuccess;
+  dim3 grid(nblk, (a.cout + BN - 1) / BN);
+  hipLaunchKernelGGL((k_conv3<T, BN, WM, WN, PH, EPI, SEG2>), grid, dim3(WM * WN * 64), 0, s, a, g);
   return hipGetLastError();
 }
 
@@ -739,10 +959,27 @@ static hipError_t run_conv(const ConvArgs &a, const Batch &g, hipStream_t s) {
   return hipGetLastError();
 }
 
+// k_conv2 tile configurations: BN output channels, WM x WN waves, PH x 32 pixel patches.
+// BF16 layers with 256 or 512 channels use 4 waves with 128 x 128 wave tiles (AGPR
+// accumulators, one wave per SIMD, long K loops); narrower layers have short K loops
+// whose staging latency a second wave per SIMD hides better, so they keep 2 waves per
+// SIMD, as FP32 does throughout.
+struct Conv2Cfg { int bn, wm, wn, ph; };
+static Conv2Cfg conv2_cfg(int precision, int cout) {
+  if (precision == 1) {
+    if (cout <= 64) return {64, 4, 1, 8};
+    if (cout % 256 == 0) return {256, 2, 2, 8};
+    return {128, 4, 2, 8};
+  }
+  if (cout <= 64) return {64, 4, 1, 8};
+  if (cout % 256 == 0) return {256, 2, 4, 8};
+  return {128, 4, 2, 8};
+}
+
 int conv_block_rows(int precision, int in_mode, int epi, int cout) {
   (void)precision;
   if (epi == EPI_STITCH) return 8;
-  if (in_mode == IN_NHWC) return 8;     // k_conv2
+  if (in_mode == IN_NHWC) return conv2_cfg(precision, cout).ph;   // k_conv2
   return cout <= 64 ? 16 : 8;
 }
 int conv_block_cols(int precision, int in_mode, int epi, int cout) {
@@ -774,28 +1011,35 @@ static hipError_t conv_dispatch(int in_mode, int epi, const ConvArgs &a, const B
       return hipGetLastError();
     }
     if (in_mode != IN_NHWC) return hipErrorInvalidValue;
-    if (small) return run_conv2<T, 64, 4, 1, EPI_FWD, false>(a, g, s);
-    if (a.cout % 256 == 0) {
-      if constexpr (sizeof(T) == 2) return run_conv2<T, 256, 2, 2, EPI_FWD, false>(a, g, s);
-      else return run_conv2<T, 256, 2, 4, EPI_FWD, false>(a, g, s);
+    if constexpr (sizeof(T) == 2) {
+      if (small) return run_conv3<T, 64, 4, 1, 8, EPI_FWD, false>(a, g, s);
+      if (a.cout % 256 == 0) return run_conv3<T, 256, 2, 2, 8, EPI_FWD, false>(a, g, s);
+      return run_conv3<T, 128, 4, 2, 8, EPI_FWD, false>(a, g, s);
+    } else {
+      if (small) return run_conv2<T, 64, 4, 1, 8, EPI_FWD, false>(a, g, s);
+      if (a.cout % 256 == 0) return run_conv2<T, 256, 2, 4, 8, EPI_FWD, false>(a, g, s);
+      return run_conv2<T, 128, 4, 2, 8, EPI_FWD, false>(a, g, s);
     }
-    return run_conv2<T, 128, 4, 2, EPI_FWD, false>(a, g, s);
   }
   // EPI_BWD
   if (in_mode == IN_NHWC) {
-    if (small)
-      return seg2 ? run_conv2<T, 64, 4, 1, EPI_BWD, true>(a, g, s)
-                  : run_conv2<T, 64, 4, 1, EPI_BWD, false>(a, g, s);
-    if (a.cout % 256 == 0) {
-      if constexpr (sizeof(T) == 2)
-        return seg2 ? run_conv2<T, 256, 2, 2, EPI_BWD, true>(a, g, s)
-                    : run_conv2<T, 256, 2, 2, EPI_BWD, false>(a, g, s);
-      else
-        return seg2 ? run_conv2<T, 256, 2, 4, EPI_BWD, true>(a, g, s)
-                    : run_conv2<T, 256, 2, 4, EPI_BWD, false>(a, g, s);
+#define NST_CONV2_BWD(BN_, WM_, WN_, PH_)                                                  \
+  return seg2 ? run_conv2<T, BN_, WM_, WN_, PH_, EPI_BWD, true>(a, g, s)                  \
+              : run_conv2<T, BN_, WM_, WN_, PH_, EPI_BWD, false>(a, g, s)
+#define NST_CONV3_BWD(BN_, WM_, WN_, PH_)                                                  \
+  return seg2 ? run_conv3<T, BN_, WM_, WN_, PH_, EPI_BWD, true>(a, g, s)                  \
+              : run_conv3<T, BN_, WM_, WN_, PH_, EPI_BWD, false>(a, g, s)
+    if constexpr (sizeof(T) == 2) {
+      if (small) NST_CONV3_BWD(64, 4, 1, 8);
+      if (a.cout % 256 == 0) NST_CONV3_BWD(256, 2, 2, 8);
+      NST_CONV3_BWD(128, 4, 2, 8);
+    } else {
+      if (small) NST_CONV2_BWD(64, 4, 1, 8);
+      if (a.cout % 256 == 0) NST_CONV2_BWD(256, 2, 4, 8);
+      NST_CONV2_BWD(128, 4, 2, 8);
     }
-    return seg2 ? run_conv2<T, 128, 4, 2, EPI_BWD, true>(a, g, s)
-                : run_conv2<T, 128, 4, 2, EPI_BWD, false>(a, g, s);
+#undef NST_CONV2_BWD
+#undef NST_CONV3_BWD
   }
   if (in_mode == IN_NONE) {
     if (small)
@@ -818,11 +1062,10 @@ const char *conv_kernel_name(int precision, int in_mode, int epi, const ConvArgs
     return o;
   }
   if (in_mode == IN_NHWC && epi != EPI_STITCH) {
-    const int bn = a.cout <= 64 ? 64 : (a.cout % 256 == 0 ? 256 : 128);
-    const int wm = bn == 256 ? 2 : 4;
-    const int wn = bn == 64 ? 1 : (bn == 256 ? (precision == 1 ? 2 : 4) : 2);
-    snprintf(o, 160, "void nst::k_conv2<%s, %d, %d, %d, %d, %s>(nst::ConvArgs, nst::Batch)",
-             precision == 1 ? "__bf16" : "float", bn, wm, wn, epi, seg2 ? "true" : "false");
+    const Conv2Cfg k = conv2_cfg(precision, a.cout);
+    snprintf(o, 160, "void nst::k_conv%d<%s, %d, %d, %d, %d, %d, %s>(nst::ConvArgs, nst::Batch)",
+             precision == 1 ? 3 : 2, precision == 1 ? "__bf16" : "float", k.bn, k.wm, k.wn, k.ph, epi,
+             seg2 ? "true" : "false");
     return o;
   }
   if (epi == EPI_STITCH) {
