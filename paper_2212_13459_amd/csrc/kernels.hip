@@ -238,67 +238,27 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a, Batch g) {
 
 // ---------------------------------------------------------------------------------------
 // Pipelined implicit-GEMM 3x3 convolution (NHWC input) on MFMA.
-//   Work block: an 8 x 32 output patch (M = 256 pixels) x BN output channels, WM x WN
-//   waves.  The K loop runs over stages (channel chunk c, filter row ky): each stage
-//   stages the 3 taps of one filter row for BN channels in LDS, and the first stage of a
-//   chunk also stages the 10 x 34 halo patch of that chunk.  Stages are double-buffered:
-//   the global loads of stage s+1 are in flight (in registers) while the MFMAs of stage s
-//   run, then land in the other LDS buffer; one barrier per stage.
+//   Work block: a PH x 32 output patch (M = 32 PH pixels) x BN output channels, WM x WN
+//   waves.  The K loop runs over stages (channel chunk c, filter row ky): each stage holds
+//   the 3 taps of one filter row for BN channels in LDS, and the first stage of a chunk
+//   also the (PH + 2) x 34 halo patch of that chunk.  Stages are double-buffered and
+//   filled by LDS DMA (global_load_lds_dwordx4: each lane's 16 bytes go straight to LDS
+//   at the wave's base + 16 x lane, no registers or LDS store instructions involved), so
+//   the next stage's loads are in flight during the whole current stage; a stage ends
+//   with a wait for the wave's own loads and one barrier.
 //   A 32-row MFMA operand block is one patch row of 32 pixels, i.e. 32 consecutive LDS
 //   rows, which gfx950 reads without bank conflicts (blocks of 2 x 16 rows with a gap
 //   between them, as a 16-wide patch gives, read at half rate).  Halo-patch rows are
-//   padded to 80 bytes, so every tap and filter-row shift of an operand block is a
-//   constant byte offset (one address register per block); weight rows are 64 bytes with
-//   the 16-byte chunk index XOR-swizzled by (row / 4) mod 4, which tap shifts (multiples
-//   of BN rows) leave unchanged.
+//   padded to 80 bytes (unit p of a chunk is row p / 5, 16-byte chunk p % 5; chunk 4 is
+//   padding), so every tap and filter-row shift of an operand block is a constant byte
+//   offset; weight rows are 64 bytes with the 16-byte chunk XOR-swizzled by (row / 4)
+//   mod 4 (applied on the global side of the DMA), which tap shifts (multiples of BN
+//   rows) leave unchanged.  Halo positions outside the window and padding units read a
+//   zero row.
 //   Segment 1 (optional) adds the centre tap over in2 (the style residual V D~).
 // ---------------------------------------------------------------------------------------
-// Branch-free stage loads: every lane loads from a valid (clamped) address and selects
-// zero outside the window, so the compiler can track the in-flight loads exactly and
-// overlap them with the MFMAs of the current stage.
-// Halo-patch staging: vector v = tid + i NT covers patch row 16 (v / 64) + v % 16 and
-// 16-byte chunk (v / 16) % 4, so the 16 lanes of each LDS write phase store 16 different
-// rows of the padded layout (row stride CK + VEC elements = 80 bytes, no bank conflicts).
-// Loads are a uniform base (block origin, channel chunk) plus a 32-bit per-lane byte
-// offset; lanes outside the window load a clamped (valid) pixel and select zero.
-template <typename T, int NT, int ANV, int VEC>
-__device__ __forceinline__ void stage_load_a(u32x4 (&ra)[ANV], const T *base, const unsigned (&arel)[ANV],
-                                             const unsigned (&amask)[ANV], int cin, int apart) {
-#pragma unroll
-  for (int i = 0; i < ANV; ++i) {
-    const unsigned off = (arel[i] * (unsigned)cin + (unsigned)(apart * VEC)) * (unsigned)sizeof(T);
-    ra[i] = *(const u32x4 *)((const char *)base + off) & amask[i];
-  }
-}
-
-template <int BNV>
-__device__ __forceinline__ void stage_load_b(u32x4 (&rb)[BNV], const void *base, const unsigned (&boff)[BNV]) {
-#pragma unroll
-  for (int i = 0; i < BNV; ++i) rb[i] = *(const u32x4 *)((const char *)base + boff[i]);
-}
-
-template <typename T, int NT, int ANV, int AROWS, int CK, int VEC>
-__device__ __forceinline__ void stage_store_a(T *dst, const u32x4 (&r)[ANV], int tid) {
-#pragma unroll
-  for (int i = 0; i < ANV; ++i) {
-    const int v = tid + i * NT;
-    const int row = (v >> 6) * 16 + (v & 15), part = (v >> 4) & 3;
-    if ((i + 1) * NT <= AROWS * 4 || row < AROWS)
-      *(u32x4 *)(&dst[row * (CK + VEC) + part * VEC]) = r[i];
-  }
-}
-
 __device__ __forceinline__ int swz64(int row, int chunk, int ck, int vec) {
   return row * ck + ((chunk ^ ((row >> 2) & 3)) * vec);
-}
-
-template <typename T, int NT, int NV, int CK, int VEC>
-__device__ __forceinline__ void stage_store(T *dst, const u32x4 (&r)[NV], int tid) {
-#pragma unroll
-  for (int i = 0; i < NV; ++i) {
-    const int v = tid + i * NT;
-    *(u32x4 *)(&dst[swz64(v >> 2, v & 3, CK, VEC)]) = r[i];
-  }
 }
 
 // One k-step of a stage: filter tap ti, channel half kh of the 64-byte LDS rows (16 BF16
@@ -338,53 +298,12 @@ __device__ __forceinline__ void mma_kstep(f32x16 (&acc)[TM][TN], const KFrag<TM,
     }
 }
 
-// The MFMAs of one stage (NTAP taps at LDS pixel offsets toff0 + ti) as a software
-// pipeline over its 2 NTAP k-steps: the fragments of k-step j + 1 are read while the
-// MFMAs of k-step j run (the scheduling barrier keeps later reads from being hoisted,
-// which would cost registers).  The registers staged for the next stage (loaded by the
-// caller before this stage) are written to their LDS buffers at the second-to-last
-// k-step, so only the barrier remains at the end of the stage.
-template <typename T, int TM, int TN, int BN, int CK, int VEC, int NTAP, int NT, int ANV, int BNV,
-          int AROWS, bool SA, bool SB>
-__device__ __forceinline__ void stage_pipe(f32x16 (&acc)[TM][TN], const T *A, const T *B,
-                                           const int (&pidx)[TM], int toff0, int bcol, int half,
-                                           const u32x4 (&ra)[ANV], const u32x4 (&rb)[BNV], T *adst,
-                                           T *bdst, bool store, int tid) {
-  constexpr int NK = 2 * NTAP;
-  constexpr int JS = NK >= 2 ? NK - 2 : 0;
-  KFrag<TM, TN> f[2];
-  load_kstep<T, TM, TN, BN, CK, VEC>(f[0], A, B, pidx, toff0, 0, 0, bcol, half);
-#pragma unroll
-  for (int j = 0; j < NK; ++j) {
-    if (j + 1 < NK)
-      load_kstep<T, TM, TN, BN, CK, VEC>(f[(j + 1) & 1], A, B, pidx, toff0 + (j + 1) / 2, (j + 1) / 2,
-                                         (j + 1) & 1, bcol, half);
-    mma_kstep<T, TM, TN>(acc, f[j & 1]);
-    if (j == JS && store) {
-      if constexpr (SA) stage_store_a<T, NT, ANV, AROWS, CK, VEC>(adst, ra, tid);
-      if constexpr (SB) stage_store<T, NT, BNV, CK, VEC>(bdst, rb, tid);
-    }
-    __builtin_amdgcn_sched_barrier(0);
-  }
-}
-
 // Passes of the LDS epilogue: the fewest that divide TN and fit the FP32 tile
 // (BM x (WN x TN / passes x 32 + 8) floats) into the stage buffers.
 constexpr int epi_passes(int bm, int wn, int tn, int smem_bytes) {
   for (int p = 1; p <= tn; ++p)
     if (tn % p == 0 && bm * (wn * (tn / p) * 32 + 8) * 4 <= smem_bytes) return p;
   return 0;
-}
-
-// Weight-row offsets of a one-tap-row stage (segment 1): rows past BN duplicate row % BN.
-template <typename T, int NT, int BNV, int BN, int CK, int VEC>
-__device__ __forceinline__ void seg_boff(unsigned (&boff)[BNV], int cout_pad, int n0, int tid) {
-  (void)cout_pad;
-#pragma unroll
-  for (int i = 0; i < BNV; ++i) {
-    const int n = ((tid + i * NT) >> 2) % BN;
-    boff[i] = (unsigned)(((n0 + n) * CK + (tid & 3) * VEC) * (int)sizeof(T));
-  }
 }
 
 // Conv epilogue through LDS (the caller's last barrier has released its stage buffers,
@@ -478,170 +397,6 @@ __device__ __forceinline__ void conv_epilogue(f32x16 (&acc)[PH * 32 / (WM * 32)]
   }
 }
 
-template <typename T, int BN, int WM, int WN, int PH, int EPI, bool SEG2>
-__global__ __launch_bounds__(WM * WN * 64) void k_conv2(ConvArgs a, Batch g) {
-  constexpr int PW = 32, BM = PH * PW;
-  constexpr int NT = WM * WN * 64;
-  constexpr int TM = BM / (WM * 32), TN = BN / (WN * 32);
-  static_assert(TM >= 1 && TN >= 1 && TM * WM * 32 == BM && TN * WN * 32 == BN, "bad wave tiling");
-  constexpr int CK = Tr<T>::CK;
-  constexpr int VEC = 16 / sizeof(T);
-  constexpr int HP = PH + 2, WP = PW + 2;
-  constexpr int AROWS = HP * WP;
-  constexpr int BROWS = 3 * BN;
-  constexpr int ANV = (AROWS * 4 + NT - 1) / NT;
-  constexpr int BNV = (BROWS * 4 + NT - 1) / NT;
-  constexpr int BROWS_P = BNV * NT / 4;
-  constexpr int ASZ = AROWS * (CK + VEC), BSZ = BROWS_P * CK;
-  static_assert(epi_passes(BM, WN, TN, 2 * (ASZ + BSZ) * (int)sizeof(T)) > 0, "epilogue does not fit");
-  // wide wave tiles (one wave per SIMD): accumulators in AGPRs, taps unrolled
-  constexpr bool WIDE = TM * TN >= 16;
-  __shared__ __attribute__((aligned(16))) T sm[2 * (ASZ + BSZ)];
-  if constexpr (WIDE) asm volatile("" ::: "a0");
-
-  const int t = find_tile(g, blockIdx.x);
-  const int lb = blockIdx.x - g.pfx[t];
-  const int h = g.h[t], w = g.w[t];
-  const int nbx = (w + PW - 1) / PW;
-  const int y0 = (lb / nbx) * PH, x0 = (lb % nbx) * PW;
-  const int n0 = blockIdx.y * BN;
-  const long long slot = g.slot[t];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave / WN, wn = wave % WN;
-  const int l32 = lane & 31, half = lane >> 5;
-
-  int pidx[TM];
-#pragma unroll
-  for (int tm = 0; tm < TM; ++tm) {
-    const int m = wm * TM * 32 + tm * 32 + l32;
-    pidx[tm] = (m / PW) * WP + (m % PW);
-  }
-
-  f32x16 acc[TM][TN];
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
-
-  const T *in0 = (const T *)a.in + slot * a.in_ss;
-  const T *in1 = SEG2 ? (const T *)a.in2 + slot * a.in2_ss : nullptr;
-  const T *wp0 = (const T *)a.wp;
-  const T *wp1 = (const T *)a.wp2;
-  const int nck = a.cin / CK;
-  const int nck2 = SEG2 ? a.cin2 / CK : 0;
-  u32x4 ra[ANV], rb[BNV];
-
-  // per-lane staging offsets, computed once: halo pixel relative to the block's clamped
-  // origin (by, bx) and its in-window mask; weight row (tap row ti < 3, channel n) offsets
-  const int by = max(y0 - 1, 0), bx = max(x0 - 1, 0);
-  const int apart = (tid >> 4) & 3;
-  unsigned arel[ANV], amask[ANV], boff[BNV];
-#pragma unroll
-  for (int i = 0; i < ANV; ++i) {
-    const int v = tid + i * NT;
-    const int pix = (v >> 6) * 16 + (v & 15);
-    const int py = pix / WP, px = pix - py * WP;
-    const int yy = y0 - 1 + py, xx = x0 - 1 + px;
-    const int cy = min(max(yy, 0), h - 1), cx = min(max(xx, 0), w - 1);
-    arel[i] = (unsigned)((cy - by) * w + (cx - bx));
-    amask[i] = (yy >= 0 && yy < h && xx >= 0 && xx < w) ? 0xffffffffu : 0u;
-  }
-#pragma unroll
-  for (int i = 0; i < BNV; ++i) {
-    const int row = (tid + i * NT) >> 2;
-    int ti = row / BN;
-    const int n = row - ti * BN;
-    ti = ti < 3 ? ti : 0;                    // rows past the stage's taps duplicate tap 0 (unused)
-    boff[i] = (unsigned)(((ti * a.cout_pad + n0 + n) * CK + (tid & 3) * VEC) * (int)sizeof(T));
-  }
-  const T *abase0 = in0 + ((long long)by * w + bx) * a.cin;
-  const long long wrow = (long long)a.cout_pad * CK;   // elements per filter tap of a chunk
-
-  // stage (c, ky) of segment 0 uses A buffer c & 1 and B buffer (3 c + ky) & 1
-  stage_load_a<T, NT, ANV, VEC>(ra, abase0, arel, amask, a.cin, apart);
-  stage_load_b<BNV>(rb, wp0, boff);
-  stage_store_a<T, NT, ANV, AROWS, CK, VEC>(sm, ra, tid);
-  stage_store<T, NT, BNV, CK, VEC>(sm + 2 * ASZ, rb, tid);
-  __syncthreads();
-  T *const A0 = sm, *const A1 = sm + ASZ, *const B0 = sm + 2 * ASZ, *const B1 = sm + 2 * ASZ + BSZ;
-  const int bcol = wn * TN * 32 + l32;
-#pragma unroll 1
-  for (int c = 0; c < nck; ++c) {
-    const bool odd = c & 1;
-    T *const Ac = odd ? A1 : A0, *const An = odd ? A0 : A1;
-    // stage index 3 c + ky selects the B buffer; 3 c is odd when c is
-    T *const Bx = odd ? B1 : B0, *const By = odd ? B0 : B1;
-    // filter row 0 (B buffer x); prefetch row 1 into y
-    stage_load_b<BNV>(rb, wp0 + (c * 9 + 3) * wrow, boff);
-    stage_pipe<T, TM, TN, BN, CK, VEC, 3, NT, ANV, BNV, AROWS, false, true>(acc, Ac, Bx, pidx, 0, bcol, half, ra,
-                                                                          rb, nullptr, By, true, tid);
-    __syncthreads();
-    // filter row 1 (y); prefetch row 2 into x
-    stage_load_b<BNV>(rb, wp0 + (c * 9 + 6) * wrow, boff);
-    stage_pipe<T, TM, TN, BN, CK, VEC, 3, NT, ANV, BNV, AROWS, false, true>(acc, Ac, By, pidx, WP, bcol, half, ra,
-                                                                          rb, nullptr, Bx, true, tid);
-    __syncthreads();
-    // filter row 2 (x); prefetch the next chunk's halo patch and row 0 (or segment 1) into
-    // the other A buffer and y
-    const bool more = c + 1 < nck;
-    const bool seg = !more && SEG2 && nck2 > 0;
-    if (more) {
-      stage_load_a<T, NT, ANV, VEC>(ra, abase0 + (c + 1) * CK, arel, amask, a.cin, apart);
-      stage_load_b<BNV>(rb, wp0 + (c + 1) * 9 * wrow, boff);
-    } else if (seg) {
-      const T *abase1 = in1 + ((long long)by * w + bx) * a.cin2;
-      stage_load_a<T, NT, ANV, VEC>(ra, abase1, arel, amask, a.cin2, apart);
-      seg_boff<T, NT, BNV, BN, CK, VEC>(boff, a.cout_pad, n0, tid);
-      stage_load_b<BNV>(rb, wp1, boff);
-    }
-    stage_pipe<T, TM, TN, BN, CK, VEC, 3, NT, ANV, BNV, AROWS, true, true>(acc, Ac, Bx, pidx, 2 * WP, bcol, half,
-                                                                         ra, rb, An, By, more || seg, tid);
-    __syncthreads();
-  }
-  if constexpr (SEG2) {
-    // segment-1 chunk c2 is stage 3 nck + c2 with A buffer (nck + c2) & 1; boff now holds
-    // the one-tap-row weight offsets
-    const T *abase1 = in1 + ((long long)by * w + bx) * a.cin2;
-#pragma unroll 1
-    for (int c2 = 0; c2 < nck2; ++c2) {
-      const int st = 3 * nck + c2, ac = nck + c2;
-      const bool more = c2 + 1 < nck2;
-      if (more) {
-        stage_load_a<T, NT, ANV, VEC>(ra, abase1 + (c2 + 1) * CK, arel, amask, a.cin2, apart);
-        stage_load_b<BNV>(rb, wp1 + (long long)(c2 + 1) * wrow, boff);
-      }
-      stage_pipe<T, TM, TN, BN, CK, VEC, 1, NT, ANV, BNV, AROWS, true, true>(
-          acc, (ac & 1) ? A1 : A0, (st & 1) ? B1 : B0, pidx, WP + 1, bcol, half, ra, rb,
-          (ac & 1) ? A0 : A1, (st & 1) ? B0 : B1, more, tid);
-      __syncthreads();
-    }
-  }
-
-  conv_epilogue<T, BN, WM, WN, PH, EPI, 2 * (ASZ + BSZ) * (int)sizeof(T)>(acc, sm, a, g, t, slot, y0, x0, h, w,
-                                                                        n0, tid, wm, wn, l32, half);
-}
-
-template <typename T, int BN, int WM, int WN, int PH, int EPI, bool SEG2>
-static hipError_t run_conv2(const ConvArgs &a, const Batch &g, hipStream_t s) {
-  const int nblk = g.pfx[g.n];
-  if (nblk == 0) return hipSuccess;
-  dim3 grid(nblk, (a.cout + BN - 1) / BN);
-  hipLaunchKernelGGL((k_conv2<T, BN, WM, WN, PH, EPI, SEG2>), grid, dim3(WM * WN * 64), 0, s, a, g);
-  return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------------------
-// The same convolution with its stages filled by LDS DMA (global_load_lds_dwordx4): each
-// lane's 16 bytes go straight to LDS at the wave's base + 16 x lane, so no registers hold
-// staged data and no LDS store instructions are issued; the next stage's loads are in
-// flight during the whole current stage, and a stage ends with a wait for this wave's
-// loads and the barrier.  Layouts are those of k_conv2: the halo patch in 80-byte rows
-// (unit p of a chunk is row p / 5, 16-byte chunk p % 5; chunk 4 is padding), weights in
-// 64-byte rows with the chunk XOR-swizzled by (row / 4) mod 4, applied on the global side.
-// Halo positions outside the window and padding units read a zero row.
-// ---------------------------------------------------------------------------------------
 __device__ __attribute__((aligned(16))) unsigned kZeroRow[4] = {0u, 0u, 0u, 0u};
 
 typedef __attribute__((address_space(3))) void lds_void;
@@ -959,7 +714,7 @@ static hipError_t run_conv(const ConvArgs &a, const Batch &g, hipStream_t s) {
   return hipGetLastError();
 }
 
-// k_conv2 tile configurations: BN output channels, WM x WN waves, PH x 32 pixel patches.
+// k_conv3 tile configurations: BN output channels, WM x WN waves, PH x 32 pixel patches.
 // BF16 layers with 256 or 512 channels use 4 waves with 128 x 128 wave tiles (AGPR
 // accumulators, one wave per SIMD, long K loops); narrower layers have short K loops
 // whose staging latency a second wave per SIMD hides better, so they keep 2 waves per
@@ -979,7 +734,7 @@ static Conv2Cfg conv2_cfg(int precision, int cout) {
 int conv_block_rows(int precision, int in_mode, int epi, int cout) {
   (void)precision;
   if (epi == EPI_STITCH) return 8;
-  if (in_mode == IN_NHWC) return conv2_cfg(precision, cout).ph;   // k_conv2
+  if (in_mode == IN_NHWC) return conv2_cfg(precision, cout).ph;   // k_conv3
   return cout <= 64 ? 16 : 8;
 }
 int conv_block_cols(int precision, int in_mode, int epi, int cout) {
@@ -1016,16 +771,13 @@ static hipError_t conv_dispatch(int in_mode, int epi, const ConvArgs &a, const B
       if (a.cout % 256 == 0) return run_conv3<T, 256, 2, 2, 8, EPI_FWD, false>(a, g, s);
       return run_conv3<T, 128, 4, 2, 8, EPI_FWD, false>(a, g, s);
     } else {
-      if (small) return run_conv2<T, 64, 4, 1, 8, EPI_FWD, false>(a, g, s);
-      if (a.cout % 256 == 0) return run_conv2<T, 256, 2, 4, 8, EPI_FWD, false>(a, g, s);
-      return run_conv2<T, 128, 4, 2, 8, EPI_FWD, false>(a, g, s);
+      if (small) return run_conv3<T, 64, 4, 1, 8, EPI_FWD, false>(a, g, s);
+      if (a.cout % 256 == 0) return run_conv3<T, 256, 2, 4, 8, EPI_FWD, false>(a, g, s);
+      return run_conv3<T, 128, 4, 2, 8, EPI_FWD, false>(a, g, s);
     }
   }
   // EPI_BWD
   if (in_mode == IN_NHWC) {
-#define NST_CONV2_BWD(BN_, WM_, WN_, PH_)                                                  \
-  return seg2 ? run_conv2<T, BN_, WM_, WN_, PH_, EPI_BWD, true>(a, g, s)                  \
-              : run_conv2<T, BN_, WM_, WN_, PH_, EPI_BWD, false>(a, g, s)
 #define NST_CONV3_BWD(BN_, WM_, WN_, PH_)                                                  \
   return seg2 ? run_conv3<T, BN_, WM_, WN_, PH_, EPI_BWD, true>(a, g, s)                  \
               : run_conv3<T, BN_, WM_, WN_, PH_, EPI_BWD, false>(a, g, s)
@@ -1034,11 +786,10 @@ static hipError_t conv_dispatch(int in_mode, int epi, const ConvArgs &a, const B
       if (a.cout % 256 == 0) NST_CONV3_BWD(256, 2, 2, 8);
       NST_CONV3_BWD(128, 4, 2, 8);
     } else {
-      if (small) NST_CONV2_BWD(64, 4, 1, 8);
-      if (a.cout % 256 == 0) NST_CONV2_BWD(256, 2, 4, 8);
-      NST_CONV2_BWD(128, 4, 2, 8);
+      if (small) NST_CONV3_BWD(64, 4, 1, 8);
+      if (a.cout % 256 == 0) NST_CONV3_BWD(256, 2, 4, 8);
+      NST_CONV3_BWD(128, 4, 2, 8);
     }
-#undef NST_CONV2_BWD
 #undef NST_CONV3_BWD
   }
   if (in_mode == IN_NONE) {
@@ -1063,9 +814,8 @@ const char *conv_kernel_name(int precision, int in_mode, int epi, const ConvArgs
   }
   if (in_mode == IN_NHWC && epi != EPI_STITCH) {
     const Conv2Cfg k = conv2_cfg(precision, a.cout);
-    snprintf(o, 160, "void nst::k_conv%d<%s, %d, %d, %d, %d, %d, %s>(nst::ConvArgs, nst::Batch)",
-             precision == 1 ? 3 : 2, precision == 1 ? "__bf16" : "float", k.bn, k.wm, k.wn, k.ph, epi,
-             seg2 ? "true" : "false");
+    snprintf(o, 160, "void nst::k_conv3<%s, %d, %d, %d, %d, %d, %s>(nst::ConvArgs, nst::Batch)",
+             precision == 1 ? "__bf16" : "float", k.bn, k.wm, k.wn, k.ph, epi, seg2 ? "true" : "false");
     return o;
   }
   if (epi == EPI_STITCH) {
