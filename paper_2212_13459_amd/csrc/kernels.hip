@@ -439,20 +439,19 @@ __device__ __forceinline__ void dma_boff(unsigned (&boff)[BNV], int nrows, int c
   }
 }
 
-// One stage: issue the next stage's DMA (if any), then the k-step pipeline over this
-// stage's buffers, then wait for this wave's DMA (the caller's barrier follows).
+// One stage: issue DMA (weights for the next stage, then optionally a halo chunk), then
+// the k-step pipeline over this stage's buffers, then wait for this wave's DMA except the
+// last VMW loads (the caller's barrier follows).
 template <typename T, int TM, int TN, int BN, int CK, int VEC, int NTAP, int NT, int ANVD, int AUNITS, int BNV,
-          bool DA, bool DB>
+          bool DA, int VMW>
 __device__ __forceinline__ void stage_dma(f32x16 (&acc)[TM][TN], const T *__restrict__ A,
                                           const T *__restrict__ B, const int (&pidx)[TM], int toff0, int bcol,
                                           int half, T *__restrict__ adst, const T *abase,
                                           const unsigned (&arel)[ANVD], unsigned okbits, int cin,
                                           T *__restrict__ bdst, const T *wbase, const unsigned (&boff)[BNV],
-                                          bool issue, int wv, int tid) {
-  if (issue) {
-    if constexpr (DA) dma_a<T, NT, ANVD, AUNITS, VEC>(adst, abase, arel, okbits, cin, wv, tid);
-    if constexpr (DB) dma_b<T, NT, BNV, VEC>(bdst, wbase, boff, wv);
-  }
+                                          bool issue_b, bool issue_a, int wv, int tid) {
+  if (issue_b) dma_b<T, NT, BNV, VEC>(bdst, wbase, boff, wv);
+  if (DA && issue_a) dma_a<T, NT, ANVD, AUNITS, VEC>(adst, abase, arel, okbits, cin, wv, tid);
   __builtin_amdgcn_sched_barrier(0);
   constexpr int NK = 2 * NTAP;
   KFrag<TM, TN> f[2];
@@ -465,7 +464,12 @@ __device__ __forceinline__ void stage_dma(f32x16 (&acc)[TM][TN], const T *__rest
     mma_kstep<T, TM, TN>(acc, f[j & 1]);
     __builtin_amdgcn_sched_barrier(0);
   }
-  __builtin_amdgcn_s_waitcnt(0);
+  // wait for this wave's loads; a halo chunk issued in this stage (the last VMW loads, as
+  // loads complete in issue order) may stay in flight
+  if (DA && issue_a)
+    __builtin_amdgcn_s_waitcnt(0xf70 | VMW);
+  else
+    __builtin_amdgcn_s_waitcnt(0xf70);
 }
 
 template <typename T, int BN, int WM, int WN, int PH, int EPI, bool SEG2>
@@ -546,27 +550,34 @@ __global__ __launch_bounds__(WM * WN * 64) void k_conv3(ConvArgs a, Batch g) {
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   const int bcol = wn * TN * 32 + l32;
+  // halo loads the slowest wave issues per chunk (a stage may leave them in flight)
+  constexpr int AMIN = (AUNITS - (NT / 64 - 1) * 64 + NT - 1) / NT;
+  static_assert(AMIN >= 1 && AMIN <= 15, "vmcnt range");
 #pragma unroll 1
   for (int c = 0; c < nck; ++c) {
     const bool odd = c & 1;
     T *const Ac = odd ? A1 : A0, *const An = odd ? A0 : A1;
     T *const Bx = odd ? B1 : B0, *const By = odd ? B0 : B1;
-    stage_dma<T, TM, TN, BN, CK, VEC, 3, NT, ANVD, AUNITS, BNV, false, true>(
-        acc, Ac, Bx, pidx, 0, bcol, half, nullptr, nullptr, arel, okbits, 0, By, wp0 + (c * 9 + 3) * wrow, boff,
-        true, wv, tid);
-    __syncthreads();
-    stage_dma<T, TM, TN, BN, CK, VEC, 3, NT, ANVD, AUNITS, BNV, false, true>(
-        acc, Ac, By, pidx, WP, bcol, half, nullptr, nullptr, arel, okbits, 0, Bx, wp0 + (c * 9 + 6) * wrow, boff,
-        true, wv, tid);
-    __syncthreads();
     const bool more = c + 1 < nck;
     const bool seg = !more && SEG2 && nck2 > 0;
-    if (seg) dma_boff<T, NT, BNV, BN, CK, VEC>(boff, 1, a.cout_pad, n0, tid);
+    // filter row 0 (B buffer x): prefetch row 1 into y, then the next chunk's halo patch
+    // (or segment 1's) into the other A buffer, which has two stages to arrive
     const T *anext = more ? abase0 + (c + 1) * CK : (SEG2 ? in1 + ((long long)by * w + bx) * a.cin2 : abase0);
+    stage_dma<T, TM, TN, BN, CK, VEC, 3, NT, ANVD, AUNITS, BNV, true, AMIN>(
+        acc, Ac, Bx, pidx, 0, bcol, half, An, anext, arel, okbits, more ? a.cin : a.cin2, By,
+        wp0 + (c * 9 + 3) * wrow, boff, true, more || seg, wv, tid);
+    __syncthreads();
+    // filter row 1 (y); prefetch row 2 into x (the halo patch lands with it)
+    stage_dma<T, TM, TN, BN, CK, VEC, 3, NT, ANVD, AUNITS, BNV, false, 0>(
+        acc, Ac, By, pidx, WP, bcol, half, nullptr, nullptr, arel, okbits, 0, Bx, wp0 + (c * 9 + 6) * wrow, boff,
+        true, false, wv, tid);
+    __syncthreads();
+    // filter row 2 (x); prefetch the next chunk's row 0 (or segment 1's weights) into y
+    if (seg) dma_boff<T, NT, BNV, BN, CK, VEC>(boff, 1, a.cout_pad, n0, tid);
     const T *wnext = more ? wp0 + (c + 1) * 9 * wrow : wp1;
-    stage_dma<T, TM, TN, BN, CK, VEC, 3, NT, ANVD, AUNITS, BNV, true, true>(
-        acc, Ac, Bx, pidx, 2 * WP, bcol, half, An, anext, arel, okbits, more ? a.cin : a.cin2, By, wnext, boff,
-        more || seg, wv, tid);
+    stage_dma<T, TM, TN, BN, CK, VEC, 3, NT, ANVD, AUNITS, BNV, false, 0>(
+        acc, Ac, Bx, pidx, 2 * WP, bcol, half, nullptr, nullptr, arel, okbits, 0, By, wnext, boff, more || seg,
+        false, wv, tid);
     __syncthreads();
   }
   if constexpr (SEG2) {
@@ -575,10 +586,10 @@ __global__ __launch_bounds__(WM * WN * 64) void k_conv3(ConvArgs a, Batch g) {
     for (int c2 = 0; c2 < nck2; ++c2) {
       const int st = 3 * nck + c2, ac = nck + c2;
       const bool more = c2 + 1 < nck2;
-      stage_dma<T, TM, TN, BN, CK, VEC, 1, NT, ANVD, AUNITS, BNV, true, true>(
+      stage_dma<T, TM, TN, BN, CK, VEC, 1, NT, ANVD, AUNITS, BNV, true, 0>(
           acc, (ac & 1) ? A1 : A0, (st & 1) ? B1 : B0, pidx, WP + 1, bcol, half, (ac & 1) ? A0 : A1,
           abase1 + (c2 + 1) * CK, arel, okbits, a.cin2, (st & 1) ? B0 : B1, wp1 + (long long)(c2 + 1) * wrow,
-          boff, more, wv, tid);
+          boff, more, more, wv, tid);
       __syncthreads();
     }
   }
