@@ -495,8 +495,11 @@ __global__ __launch_bounds__(WM * WN * 64) void k_conv3(ConvArgs a, Batch g) {
   const int t = find_tile(g, blockIdx.x);
   const int lb = blockIdx.x - g.pfx[t];
   const int h = g.h[t], w = g.w[t];
-  const int nbx = (w + PW - 1) / PW;
-  const int y0 = (lb / nbx) * PH, x0 = (lb % nbx) * PW;
+  // output region: the window, or for the image-gradient stitch the tile's owned pixels
+  const int oy = EPI == EPI_STITCH ? g.a0[t] : 0, ox = EPI == EPI_STITCH ? g.a2[t] : 0;
+  const int ey = EPI == EPI_STITCH ? g.a1[t] : h, ex = EPI == EPI_STITCH ? g.a3[t] : w;
+  const int nbx = (ex - ox + PW - 1) / PW;
+  const int y0 = oy + (lb / nbx) * PH, x0 = ox + (lb % nbx) * PW;
   const int n0 = blockIdx.y * BN;
   const long long slot = g.slot[t];
   const int tid = threadIdx.x, lane = tid & 63;
@@ -593,8 +596,21 @@ __global__ __launch_bounds__(WM * WN * 64) void k_conv3(ConvArgs a, Batch g) {
       __syncthreads();
     }
   }
-  conv_epilogue<T, BN, WM, WN, PH, EPI, 2 * (ASZ + BSZ) * (int)sizeof(T)>(acc, sm, a, g, t, slot, y0, x0, h, w,
-                                                                        n0, tid, wm, wn, l32, half);
+  if constexpr (EPI == EPI_STITCH) {
+    // image gradient (FP32 CHW) at the owned pixels: output columns 0..2 of the padded 32
+#pragma unroll
+    for (int tm = 0; tm < TM; ++tm)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int m = wm * TM * 32 + tm * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+        const int py = y0 + m / PW, px = x0 + m % PW;
+        if (l32 < 3 && py < ey && px < ex)
+          a.grad[((long long)l32 * a.img_h + (g.gy[t] + py)) * a.img_w + (g.gx[t] + px)] = acc[tm][0][r];
+      }
+  } else {
+    conv_epilogue<T, BN, WM, WN, PH, EPI, 2 * (ASZ + BSZ) * (int)sizeof(T)>(acc, sm, a, g, t, slot, y0, x0, h,
+                                                                          w, n0, tid, wm, wn, l32, half);
+  }
 }
 
 template <typename T, int BN, int WM, int WN, int PH, int EPI, bool SEG2>
@@ -608,27 +624,32 @@ static hipError_t run_conv3(const ConvArgs &a, const Batch &g, hipStream_t s) {
 
 // ---------------------------------------------------------------------------------------
 // conv1_1 forward straight from the whole FP32 CHW image (fuses the halo crop).
-//   Work block: a 16 x 16 output patch x all 64 output channels, 4 waves (64 px x 64 ch
+//   Work block: an 8 x 32 output patch x all 64 output channels, 4 waves (64 px x 64 ch
 //   each).  Thread t owns pixel t of the patch and writes its im2col row of the 27
 //   (filter tap, colour) values, zero-padded to 32, into LDS; the 64 x 32 weight operand
-//   follows; then K = 32 runs on MFMA and the epilogue applies bias + ReLU.
+//   follows; then K = 32 runs on MFMA and the LDS epilogue applies bias + ReLU and
+//   writes 16-byte rows of channels.
 // ---------------------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void k_conv_img(ConvArgs a, Batch g) {
-  constexpr int PW = 16, BM = 256, BN = 64, TM = 2, TN = 2, KP = 32;
+  constexpr int PH = 8, PW = 32, BM = 256, BN = 64, TM = 2, TN = 2, KP = 32;
   constexpr int RS = KP + 16 / (int)sizeof(T);         // LDS row stride (elements), 16 B pad
-  __shared__ __attribute__((aligned(16))) T As[BM * RS];
-  __shared__ __attribute__((aligned(16))) T Bs[BN * RS];
+  // operands, then the two-pass FP32 epilogue tile
+  constexpr int SMEM = (BM + BN) * RS * (int)sizeof(T) > BM * (32 + 8) * 4 ? (BM + BN) * RS * (int)sizeof(T)
+                                                                           : BM * (32 + 8) * 4;
+  __shared__ __attribute__((aligned(16))) unsigned char smem[SMEM];
+  T *const As = (T *)smem;
+  T *const Bs = As + BM * RS;
   const int t = find_tile(g, blockIdx.x);
   const int lb = blockIdx.x - g.pfx[t];
   const int h = g.h[t], w = g.w[t];
   const int nbx = (w + PW - 1) / PW;
-  const int y0 = (lb / nbx) * 16, x0 = (lb % nbx) * PW;
+  const int y0 = (lb / nbx) * PH, x0 = (lb % nbx) * PW;
   const long long slot = g.slot[t];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int l32 = lane & 31, half = lane >> 5;
   {
-    const int py = y0 + (tid >> 4), px = x0 + (tid & 15);
+    const int py = y0 + tid / PW, px = x0 + tid % PW;
     T row[KP];
 #pragma unroll
     for (int k = 0; k < KP; ++k) {
@@ -699,21 +720,9 @@ __global__ __launch_bounds__(256) void k_conv_img(ConvArgs a, Batch g) {
         for (int tn = 0; tn < TN; ++tn) Mma<T>::mma(acc[tm][tn], af[tm], bfr[tn]);
     }
   }
-  const int cout = a.cout;
-#pragma unroll
-  for (int tm = 0; tm < TM; ++tm)
-#pragma unroll
-    for (int tn = 0; tn < TN; ++tn)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int m = wave * 64 + tm * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
-        const int py = y0 + m / PW, px = x0 + m % PW;
-        const int n = tn * 32 + l32;
-        if (py >= h || px >= w || n >= cout) continue;
-        const long long pix = (long long)py * w + px;
-        const float v = fmaxf(acc[tm][tn][r] + a.bias[n], 0.f);
-        ((T *)a.out)[slot * a.out_ss + pix * cout + n] = from_f<T>(v);
-      }
+  __syncthreads();   // the epilogue reuses the operand buffers
+  conv_epilogue<T, BN, 4, 1, PH, EPI_FWD, SMEM>(acc, (T *)smem, a, g, t, slot, y0, x0, h, w, 0, tid, wave, 0,
+                                                l32, half);
 }
 
 template <typename T, int PH, int BN, int WM, int WN, int IN, int EPI, bool SEG2>
@@ -744,13 +753,13 @@ static Conv2Cfg conv2_cfg(int precision, int cout) {
 
 int conv_block_rows(int precision, int in_mode, int epi, int cout) {
   (void)precision;
-  if (epi == EPI_STITCH) return 8;
+  if (epi == EPI_STITCH || in_mode == IN_IMAGE) return 8;   // k_conv3 stitch, k_conv_img
   if (in_mode == IN_NHWC) return conv2_cfg(precision, cout).ph;   // k_conv3
   return cout <= 64 ? 16 : 8;
 }
 int conv_block_cols(int precision, int in_mode, int epi, int cout) {
   (void)precision; (void)cout;
-  return (in_mode == IN_NHWC && epi != EPI_STITCH) ? 32 : 16;
+  return (in_mode == IN_NHWC || in_mode == IN_IMAGE) ? 32 : 16;
 }
 int conv_block_px(int precision, int in_mode, int epi, int cout) {
   return conv_block_cols(precision, in_mode, epi, cout) * conv_block_rows(precision, in_mode, epi, cout);
@@ -763,8 +772,8 @@ static hipError_t conv_dispatch(int in_mode, int epi, const ConvArgs &a, const B
                                 hipStream_t s) {
   const bool seg2 = a.in2 != nullptr && a.cin2 > 0;
   if (epi == EPI_STITCH) {
-    if (in_mode != IN_NHWC || seg2) return hipErrorInvalidValue;
-    return run_conv<T, 8, 32, 4, 1, IN_NHWC, EPI_STITCH, false>(a, g, s);
+    if (in_mode != IN_NHWC || seg2 || a.cout > 3 || a.cout_pad != 32) return hipErrorInvalidValue;
+    return run_conv3<T, 32, 4, 1, 8, EPI_STITCH, false>(a, g, s);
   }
   const bool small = a.cout <= 64;
   if (epi == EPI_FWD) {
@@ -830,7 +839,9 @@ const char *conv_kernel_name(int precision, int in_mode, int epi, const ConvArgs
     return o;
   }
   if (epi == EPI_STITCH) {
-    ph = 8; bn = 32; wm = 4; wn = 1;
+    snprintf(o, 160, "void nst::k_conv3<%s, 32, 4, 1, 8, %d, false>(nst::ConvArgs, nst::Batch)",
+             precision == 1 ? "__bf16" : "float", EPI_STITCH);
+    return o;
   } else if (a.cout <= 64) {
     ph = 16; bn = 64; wm = 4; wn = 1;
   } else {

@@ -536,7 +536,8 @@ struct Runner {
   }
   hipError_t conv(int in_mode, int epi, const ConvArgs &a, const Batch &b) {
     double px = 0;
-    for (int k = 0; k < b.n; ++k) px += (double)b.h[k] * b.w[k];
+    for (int k = 0; k < b.n; ++k)
+      px += epi == EPI_STITCH ? (double)(b.a1[k] - b.a0[k]) * (b.a3[k] - b.a2[k]) : (double)b.h[k] * b.w[k];
     const double es = (double)L.es;
     double mac, in_b;
     if (in_mode == IN_IMAGE) {
@@ -588,8 +589,12 @@ struct Runner {
     const int ph = conv_block_rows(c->prec, in_mode, epi, cout);
     const int pw = conv_block_cols(c->prec, in_mode, epi, cout);
     b.pfx[0] = 0;
-    for (int k = 0; k < b.n; ++k)
-      b.pfx[k + 1] = b.pfx[k] + ((b.h[k] + ph - 1) / ph) * ((b.w[k] + pw - 1) / pw);
+    for (int k = 0; k < b.n; ++k) {
+      // the image-gradient stitch covers only the tile's owned pixels
+      const int rh = epi == EPI_STITCH ? b.a1[k] - b.a0[k] : b.h[k];
+      const int rw = epi == EPI_STITCH ? b.a3[k] - b.a2[k] : b.w[k];
+      b.pfx[k + 1] = b.pfx[k] + ((rh + ph - 1) / ph) * ((rw + pw - 1) / pw);
+    }
   }
   void items_pfx(Batch &b, const std::vector<long long> &items, int per_block) const {
     b.pfx[0] = 0;
