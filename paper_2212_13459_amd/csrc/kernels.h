@@ -39,9 +39,11 @@ struct ConvArgs {
   long long in2_ss;
   int cin2;
   const void *wp2;
-  // output
+  // output (EPI_FWD: may be null when only the pooled output is wanted)
   void *out;
   long long out_ss;
+  void *pool;                  // EPI_FWD: optional 2x2 max-pooled output (floor mode), NHWC
+  long long pool_ss;
   int cout;                    // real output channels
   int cout_pad;                // padded N of the packed operands
   const float *bias;           // EPI_FWD
@@ -70,8 +72,6 @@ const char *conv_kernel_name(int precision, int in_mode, int epi, const ConvArgs
 int conv_block_rows(int precision, int in_mode, int epi, int cout); // patch rows
 int conv_block_cols(int precision, int in_mode, int epi, int cout); // patch columns
 
-hipError_t launch_pool(int precision, const void *in, long long in_ss, void *out,
-                       long long out_ss, int C, const Batch &g, hipStream_t s);
 hipError_t launch_pool_bwd(int precision, const void *dp, long long dp_ss, const void *act,
                            long long act_ss, const float *rc, long long rc_ss, float two_alpha,
                            void *dz, long long dz_ss, int C, const Batch &g, hipStream_t s);

@@ -389,10 +389,53 @@ __device__ __forceinline__ void conv_epilogue(f32x16 (&acc)[PH * 32 / (WM * 32)]
             if (!(to_f(mk[e]) > 0.f)) v[e] = 0.f;
         }
       }
+      if (EPI == EPI_FWD && !a.out) continue;
       TV o;
 #pragma unroll
       for (int e = 0; e < VEC; ++e) o[e] = from_f<T>(v[e]);
       *(TV *)((T *)a.out + slot * a.out_ss + pix * cout + n) = o;
+    }
+    if constexpr (EPI == EPI_FWD) {
+      // phase 3: 2 x 2 max pool of the pass's channels (patch origins are even, so every
+      // pooling window lies in one patch); the values compared are the rounded post-ReLU
+      // outputs, first maximum in row-major window order, as a separate pooling pass would
+      if (a.pool) {
+        constexpr int PWO = PW / 2, PO = (PH / 2) * PWO;
+        const int ho = h >> 1, wo = w >> 1;
+        for (int i = tid; i < PO * CPR; i += NT) {
+          const int q = i / CPR, lc = (i % CPR) * VEC;
+          const int n = n0 + (lc / CW) * TN * 32 + p * CW + lc % CW;
+          const int qy = q / PWO, qx = q % PWO;
+          const int oy = (y0 >> 1) + qy, ox = (x0 >> 1) + qx;
+          if (oy >= ho || ox >= wo || n >= cout) continue;
+          float bv[VEC];
+#pragma unroll
+          for (int qq = 0; qq < VEC / 4; ++qq) {
+            const f32x4 b = *(const f32x4 *)(a.bias + n + 4 * qq);
+            bv[4 * qq] = b[0]; bv[4 * qq + 1] = b[1]; bv[4 * qq + 2] = b[2]; bv[4 * qq + 3] = b[3];
+          }
+          TV best;
+          float bf[VEC];
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk) {
+            const int m = (2 * qy + (kk >> 1)) * PW + 2 * qx + (kk & 1);
+#pragma unroll
+            for (int qq = 0; qq < VEC / 4; ++qq) {
+              const f32x4 u = *(const f32x4 *)(&so[m * RSW + lc + 4 * qq]);
+#pragma unroll
+              for (int e = 0; e < 4; ++e) {
+                const T tv = from_f<T>(fmaxf(u[e] + bv[4 * qq + e], 0.f));
+                const float f = to_f(tv);
+                if (kk == 0 || f > bf[4 * qq + e]) {
+                  bf[4 * qq + e] = f;
+                  best[4 * qq + e] = tv;
+                }
+              }
+            }
+          }
+          *(TV *)((T *)a.pool + slot * a.pool_ss + ((long long)oy * wo + ox) * cout + n) = best;
+        }
+      }
     }
   }
 }
@@ -625,8 +668,9 @@ static hipError_t run_conv3(const ConvArgs &a, const Batch &g, hipStream_t s) {
 // ---------------------------------------------------------------------------------------
 // conv1_1 forward straight from the whole FP32 CHW image (fuses the halo crop).
 //   Work block: an 8 x 32 output patch x all 64 output channels, 4 waves (64 px x 64 ch
-//   each).  Thread t owns pixel t of the patch and writes its im2col row of the 27
-//   (filter tap, colour) values, zero-padded to 32, into LDS; the 64 x 32 weight operand
+//   each).  The block stages its 3 x 10 x 34 FP32 image patch in LDS; thread t owns
+//   pixel t and writes its im2col row of the 27 (filter tap, colour) values, zero-padded
+//   to 32, into LDS; the 64 x 32 weight operand
 //   follows; then K = 32 runs on MFMA and the LDS epilogue applies bias + ReLU and
 //   writes 16-byte rows of channels.
 // ---------------------------------------------------------------------------------------
@@ -634,12 +678,15 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_conv_img(ConvArgs a, Batch g) {
   constexpr int PH = 8, PW = 32, BM = 256, BN = 64, TM = 2, TN = 2, KP = 32;
   constexpr int RS = KP + 16 / (int)sizeof(T);         // LDS row stride (elements), 16 B pad
-  // operands, then the two-pass FP32 epilogue tile
-  constexpr int SMEM = (BM + BN) * RS * (int)sizeof(T) > BM * (32 + 8) * 4 ? (BM + BN) * RS * (int)sizeof(T)
-                                                                           : BM * (32 + 8) * 4;
+  // operands and the image patch, then the two-pass FP32 epilogue tile
+  constexpr int OPS = (BM + BN) * RS * (int)sizeof(T) + 3 * (PH + 2) * (PW + 2) * 4;
+  constexpr int SMEM = OPS > BM * (32 + 8) * 4 ? OPS : BM * (32 + 8) * 4;
   __shared__ __attribute__((aligned(16))) unsigned char smem[SMEM];
+  constexpr int HP = PH + 2, WP = PW + 2;               // image patch with its 1-pixel halo
+  static_assert((BM + BN) * RS * (int)sizeof(T) + 3 * HP * WP * 4 <= SMEM, "image patch does not fit");
   T *const As = (T *)smem;
   T *const Bs = As + BM * RS;
+  float *const ip = (float *)(smem + (BM + BN) * RS * sizeof(T));
   const int t = find_tile(g, blockIdx.x);
   const int lb = blockIdx.x - g.pfx[t];
   const int h = g.h[t], w = g.w[t];
@@ -648,17 +695,25 @@ __global__ __launch_bounds__(256) void k_conv_img(ConvArgs a, Batch g) {
   const long long slot = g.slot[t];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int l32 = lane & 31, half = lane >> 5;
+  // the 3 colour planes of the (PH + 2) x (PW + 2) patch, zero outside the window
+  for (int e = tid; e < 3 * HP * WP; e += 256) {
+    const int c = e / (HP * WP), r = (e / WP) % HP, q = e % WP;
+    const int yy = y0 - 1 + r, xx = x0 - 1 + q;
+    float v = 0.f;
+    if (yy >= 0 && yy < h && xx >= 0 && xx < w)
+      v = a.img[((long long)c * a.img_h + (g.gy[t] + yy)) * a.img_w + (g.gx[t] + xx)];
+    ip[e] = v;
+  }
+  __syncthreads();
   {
-    const int py = y0 + tid / PW, px = x0 + tid % PW;
+    const int ty = tid / PW, tx = tid % PW;
     T row[KP];
 #pragma unroll
     for (int k = 0; k < KP; ++k) {
       float v = 0.f;
       if (k < 27) {
         const int tap = k / 3, c = k - 3 * (k / 3);
-        const int yy = py + tap / 3 - 1, xx = px + tap % 3 - 1;
-        if (py < h && px < w && yy >= 0 && yy < h && xx >= 0 && xx < w)
-          v = a.img[((long long)c * a.img_h + (g.gy[t] + yy)) * a.img_w + (g.gx[t] + xx)];
+        v = ip[(c * HP + ty + tap / 3) * WP + tx + tap % 3];
       }
       row[k] = from_f<T>(v);
     }
@@ -869,37 +924,6 @@ template <typename T> struct Vec {
   };
 };
 
-// 2x2 stride-2 floor-mode max pool, NHWC.  Work item = (output pixel, channel vector).
-template <typename T>
-__global__ __launch_bounds__(256) void k_pool(const T *in, long long in_ss, T *out,
-                                              long long out_ss, int C, Batch g) {
-  const int t = find_tile(g, blockIdx.x);
-  const int item = (blockIdx.x - g.pfx[t]) * 256 + threadIdx.x;
-  const int h = g.h[t], w = g.w[t], ho = h / 2, wo = w / 2;
-  constexpr int N = Vec<T>::N;
-  const int nv = C / N;
-  if (item >= ho * wo * nv) return;
-  const int v = item % nv, p = item / nv, oy = p / wo, ox = p - oy * wo;
-  const T *b = in + g.slot[t] * in_ss;
-  Vec<T> q[4], r;
-#pragma unroll
-  for (int k = 0; k < 4; ++k)
-    q[k].u = *(const uint4 *)(b + ((long long)(2 * oy + (k >> 1)) * w + 2 * ox + (k & 1)) * C + v * N);
-#pragma unroll
-  for (int j = 0; j < N; ++j) {
-    float m = to_f(q[0].e[j]);
-    T mv = q[0].e[j];
-#pragma unroll
-    for (int k = 1; k < 4; ++k)
-      if (to_f(q[k].e[j]) > m) {
-        m = to_f(q[k].e[j]);
-        mv = q[k].e[j];
-      }
-    r.e[j] = mv;
-  }
-  *(uint4 *)(out + g.slot[t] * out_ss + ((long long)oy * wo + ox) * C + v * N) = r.u;
-}
-
 // Max-pool backward fused with the content seed and the ReLU mask of the pre-pool layer:
 //   dZ = ([p is the first maximum of its window] dP + 2 alpha rc) * [A > 0]
 // Work item = (pooling window, channel vector); windows cut by floor mode get dP = 0.
@@ -957,19 +981,6 @@ __global__ __launch_bounds__(256) void k_pool_bwd(const T *dp, long long dp_ss, 
     }
     *(uint4 *)(dz + slot * dz_ss + pix * C + v * N) = o.u;
   }
-}
-
-hipError_t launch_pool(int precision, const void *in, long long in_ss, void *out,
-                       long long out_ss, int C, const Batch &g, hipStream_t s) {
-  const int nblk = g.pfx[g.n];
-  if (nblk == 0) return hipSuccess;
-  if (precision == 1)
-    hipLaunchKernelGGL(k_pool<bf16>, dim3(nblk), dim3(256), 0, s, (const bf16 *)in, in_ss,
-                       (bf16 *)out, out_ss, C, g);
-  else
-    hipLaunchKernelGGL(k_pool<float>, dim3(nblk), dim3(256), 0, s, (const float *)in, in_ss,
-                       (float *)out, out_ss, C, g);
-  return hipGetLastError();
 }
 
 hipError_t launch_pool_bwd(int precision, const void *dp, long long dp_ss, const void *act,

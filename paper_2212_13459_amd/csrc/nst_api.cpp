@@ -548,7 +548,8 @@ struct Runner {
       in_b = ((in_mode == IN_NHWC ? a.cin : 0) + (a.in2 ? a.cin2 : 0)) * es;
     }
     const double cout = epi == EPI_STITCH ? 3.0 : (double)a.cout;
-    double out_b = epi == EPI_STITCH ? 12.0 : cout * es;
+    double out_b = epi == EPI_STITCH ? 12.0 : (a.out ? cout * es : 0.0);
+    if (a.pool) out_b += 0.25 * cout * es;
     if (a.mask) out_b += cout * es;
     if (a.rc) out_b += cout * 4.0;
     return prof(conv_kernel_name(c->prec, in_mode, epi, a), 2.0 * px * cout * mac,
@@ -607,9 +608,10 @@ struct Runner {
                          : (const void *)slot_base(L.s_act[i - 1]);
   }
 
-  int forward(int first, int n, int upto, const float *img, const float *fc) {
+  // keep_pooled: also store the full-resolution output of layers that are pooled (the
+  // backward needs them; a forward-only pass needs just the pooled maps)
+  int forward(int first, int n, int upto, const float *img, const float *fc, bool keep_pooled) {
     const size_t es = L.es;
-    const int vec = (int)(16 / es);
     for (int i = 0; i <= upto; ++i) {
       Batch b = base_batch(first, n, i);
       ConvArgs a;
@@ -631,6 +633,12 @@ struct Runner {
       a.bias = c->bias[i];
       a.out = slot_base(L.s_act[i]);
       a.out_ss = ss(es);
+      const bool pooled = g.pool[i] && i < upto;
+      if (pooled) {
+        a.pool = slot_base(L.s_pool[i]);
+        a.pool_ss = ss(es);
+        if (!keep_pooled) a.out = nullptr;
+      }
       if (i == g.content && fc) {
         a.rc = (float *)slot_base(L.s_rc);
         a.rc_ss = ss(4);
@@ -639,20 +647,6 @@ struct Runner {
       }
       conv_pfx(b, in_mode, EPI_FWD, a.cout);
       HIPCHK(conv(in_mode, EPI_FWD, a, b));
-      if (g.pool[i] && i < upto) {
-        std::vector<long long> items(n);
-        for (int k = 0; k < n; ++k)
-          items[k] = (long long)(b.h[k] / 2) * (b.w[k] / 2) * (g.cout[i] / vec);
-        items_pfx(b, items, 256);
-        double px = 0;
-        for (int k = 0; k < n; ++k) px += (double)b.h[k] * b.w[k];
-        HIPCHK(prof(c->prec == 1 ? "void nst::k_pool<__bf16>(__bf16 const*, long long, __bf16*, long long, int, nst::Batch)"
-                                 : "void nst::k_pool<float>(float const*, long long, float*, long long, int, nst::Batch)",
-                    0.0, 1.25 * px * g.cout[i] * es, [&] {
-                      return launch_pool(c->prec, slot_base(L.s_act[i]), ss(es), slot_base(L.s_pool[i]),
-                                         ss(es), g.cout[i], b, s);
-                    }));
-      }
     }
     return NST_OK;
   }
@@ -832,7 +826,7 @@ int step1(Runner &R, const float *x, const float *fc) {
   const int nt = (int)R.tiles.size();
   for (int first = 0; first < nt; first += R.L.batch) {
     const int n = std::min(R.L.batch, nt - first);
-    int st = R.forward(first, n, upto, x, fc);
+    int st = R.forward(first, n, upto, x, fc, false);
     if (st != NST_OK) return st;
     if ((st = R.grams(first, n)) != NST_OK) return st;
     if (fc && (st = R.content_energy(first, n)) != NST_OK) return st;
@@ -919,7 +913,7 @@ int nst_layer_feats(nst_ctx *ctx, const float *img, int H, int W, int T, int m, 
   const int vec = (int)(16 / R.L.es);
   for (int first = 0; first < nt; first += R.L.batch) {
     const int n = std::min(R.L.batch, nt - first);
-    if ((st = R.forward(first, n, conv, img, nullptr)) != NST_OK) return st;
+    if ((st = R.forward(first, n, conv, img, nullptr, false)) != NST_OK) return st;
     Batch b = R.base_batch(first, n, conv);
     std::vector<long long> items(n);
     for (int t = 0; t < n; ++t) items[t] = (long long)Runner::region_px(b, t) * (ctx->g.cout[conv] / vec);
@@ -979,7 +973,7 @@ int nst_loss_grad(nst_ctx *ctx, const float *x, int H, int W, const double *targ
     const int nt = (int)R.tiles.size();
     for (int first = 0; first < nt; first += R.L.batch) {
       const int n = std::min(R.L.batch, nt - first);
-      if ((st = R.forward(first, n, g.top, x, fc)) != NST_OK) return st;
+      if ((st = R.forward(first, n, g.top, x, fc, true)) != NST_OK) return st;
       if (!s1 && fc && (st = R.content_energy(first, n)) != NST_OK) return st;
       if ((st = R.backward(first, n, (float)(2.0 * alpha), use_c, grad)) != NST_OK) return st;
     }
