@@ -499,12 +499,34 @@ __device__ __forceinline__ void stage_dma(f32x16 (&acc)[TM][TN], const T *__rest
   constexpr int NK = 2 * NTAP;
   KFrag<TM, TN> f[2];
   load_kstep<T, TM, TN, BN, CK, VEC>(f[0], A, B, pidx, toff0, 0, 0, bcol, half);
+  // the next k-step's NLD fragment reads are interleaved with the first MFMAs of this
+  // k-step (R MFMAs, then one read), so they are in flight during the rest of it, the
+  // LDS counter (4 bits) never tracks two k-steps of reads, and the only LDS wait of a
+  // k-step, before its first MFMA, covers reads issued during the previous one.  With
+  // fewer than two MFMAs per read the reads all go first.
+  constexpr int NLD = TM + TN, NMF = TM * TN * (sizeof(T) == 2 ? 1 : 4);
+  constexpr int R = NMF / (2 * NLD) > 0 ? NMF / (2 * NLD) : 1;
+  constexpr int REST = NMF - NLD * R;
 #pragma unroll
   for (int j = 0; j < NK; ++j) {
     if (j + 1 < NK)
       load_kstep<T, TM, TN, BN, CK, VEC>(f[(j + 1) & 1], A, B, pidx, toff0 + (j + 1) / 2, (j + 1) / 2,
                                          (j + 1) & 1, bcol, half);
     mma_kstep<T, TM, TN>(acc, f[j & 1]);
+    if (j + 1 < NK) {
+      if constexpr (NMF >= 2 * NLD) {
+#pragma unroll
+        for (int q = 0; q < NLD; ++q) {
+          __builtin_amdgcn_sched_group_barrier(0x008, R, 0);   // R MFMAs
+          __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // one LDS read
+        }
+        if constexpr (REST > 0) __builtin_amdgcn_sched_group_barrier(0x008, REST, 0);
+      } else {
+        // few MFMAs per k-step (two waves per SIMD): all reads first
+        __builtin_amdgcn_sched_group_barrier(0x100, NLD, 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, NMF, 0);
+      }
+    }
     __builtin_amdgcn_sched_barrier(0);
   }
   // wait for this wave's loads; a halo chunk issued in this stage (the last VMW loads, as
