@@ -10,6 +10,8 @@
 // in a fixed order, so results are bitwise reproducible and independent of the batch
 // size.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 #include <stdint.h>
 #include <stdio.h>
 
@@ -557,15 +559,24 @@ __global__ __launch_bounds__(WM * WN * 64) void k_conv3(ConvArgs a, Batch g) {
   __shared__ __attribute__((aligned(16))) T sm[2 * (ASZ + BSZ)];
   if constexpr (WIDE) asm volatile("" ::: "a0");
 
-  const int t = find_tile(g, blockIdx.x);
-  const int lb = blockIdx.x - g.pfx[t];
+  // XCD-aware block order: workgroup L runs on XCD L mod 8, which takes the contiguous
+  // patch range [xcd PPX, (xcd + 1) PPX) with the NB column blocks of a patch back to
+  // back, so those re-read the patch's halo input (and neighbours their shared halo
+  // rows) from that XCD's L2
+  const int npatch = g.pfx[g.n], nbn = (a.cout + BN - 1) / BN;
+  const int ppx = (npatch + 7) / 8;
+  const int xcd = blockIdx.x & 7, seq = blockIdx.x >> 3;
+  const int patch = xcd * ppx + seq / nbn;
+  if (patch >= npatch) return;   // whole block: before any barrier
+  const int t = find_tile(g, patch);
+  const int lb = patch - g.pfx[t];
   const int h = g.h[t], w = g.w[t];
   // output region: the window, or for the image-gradient stitch the tile's owned pixels
   const int oy = EPI == EPI_STITCH ? g.a0[t] : 0, ox = EPI == EPI_STITCH ? g.a2[t] : 0;
   const int ey = EPI == EPI_STITCH ? g.a1[t] : h, ex = EPI == EPI_STITCH ? g.a3[t] : w;
   const int nbx = (ex - ox + PW - 1) / PW;
   const int y0 = oy + (lb / nbx) * PH, x0 = ox + (lb % nbx) * PW;
-  const int n0 = blockIdx.y * BN;
+  const int n0 = (seq % nbn) * BN;
   const long long slot = g.slot[t];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -682,65 +693,61 @@ template <typename T, int BN, int WM, int WN, int PH, int EPI, bool SEG2>
 static hipError_t run_conv3(const ConvArgs &a, const Batch &g, hipStream_t s) {
   const int nblk = g.pfx[g.n];
   if (nblk == 0) return hipSuccess;
-  dim3 grid(nblk, (a.cout + BN - 1) / BN);
+  // one-dimensional grid in XCD-aware order (see k_conv3)
+  dim3 grid(8 * ((nblk + 7) / 8) * ((a.cout + BN - 1) / BN));
   hipLaunchKernelGGL((k_conv3<T, BN, WM, WN, PH, EPI, SEG2>), grid, dim3(WM * WN * 64), 0, s, a, g);
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------------------
 // conv1_1 forward straight from the whole FP32 CHW image (fuses the halo crop).
-//   Work block: an 8 x 32 output patch x all 64 output channels, 4 waves (64 px x 64 ch
-//   each).  The block stages its 3 x 10 x 34 FP32 image patch in LDS; thread t owns
-//   pixel t and writes its im2col row of the 27 (filter tap, colour) values, zero-padded
-//   to 32, into LDS; the 64 x 32 weight operand
-//   follows; then K = 32 runs on MFMA and the LDS epilogue applies bias + ReLU and
-//   writes 16-byte rows of channels.
+//   Work item: an 8 x 32 output patch x all 64 output channels, 4 waves (64 px x 64 ch
+//   each).  Persistent blocks: a block loads the 64 x 32 weight operand once, then loops
+//   over patches.  For each it stages the 3 x 10 x 34 FP32 image patch in LDS (the values
+//   were loaded into registers during the previous patch), thread t writes pixel t's
+//   im2col row of the 27 (filter tap, colour) values, zero-padded to 32, K = 32 runs on
+//   MFMA, and the LDS epilogue applies bias + ReLU and writes 16-byte rows of channels.
 // ---------------------------------------------------------------------------------------
+constexpr int kImgBlocksPerCU = 2;   // resident blocks per CU (registers: 2 waves per SIMD)
+
 template <typename T>
-__global__ __launch_bounds__(256) void k_conv_img(ConvArgs a, Batch g) {
-  constexpr int PH = 8, PW = 32, BM = 256, BN = 64, TM = 2, TN = 2, KP = 32;
-  constexpr int RS = KP + 16 / (int)sizeof(T);         // LDS row stride (elements), 16 B pad
-  // operands and the image patch, then the two-pass FP32 epilogue tile
-  constexpr int OPS = (BM + BN) * RS * (int)sizeof(T) + 3 * (PH + 2) * (PW + 2) * 4;
-  constexpr int SMEM = OPS > BM * (32 + 8) * 4 ? OPS : BM * (32 + 8) * 4;
-  __shared__ __attribute__((aligned(16))) unsigned char smem[SMEM];
-  constexpr int HP = PH + 2, WP = PW + 2;               // image patch with its 1-pixel halo
-  static_assert((BM + BN) * RS * (int)sizeof(T) + 3 * HP * WP * 4 <= SMEM, "image patch does not fit");
-  T *const As = (T *)smem;
-  T *const Bs = As + BM * RS;
-  float *const ip = (float *)(smem + (BM + BN) * RS * sizeof(T));
-  const int t = find_tile(g, blockIdx.x);
-  const int lb = blockIdx.x - g.pfx[t];
+__device__ __forceinline__ void img_patch_load(float (&v)[4], const ConvArgs &a, const Batch &g, int patch,
+                                               int tid) {
+  constexpr int PH = 8, PW = 32, HP = PH + 2, WP = PW + 2;
+  const int t = find_tile(g, patch);
+  const int lb = patch - g.pfx[t];
   const int h = g.h[t], w = g.w[t];
   const int nbx = (w + PW - 1) / PW;
   const int y0 = (lb / nbx) * PH, x0 = (lb % nbx) * PW;
-  const long long slot = g.slot[t];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int l32 = lane & 31, half = lane >> 5;
-  // the 3 colour planes of the (PH + 2) x (PW + 2) patch, zero outside the window
-  for (int e = tid; e < 3 * HP * WP; e += 256) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int e = tid + i * 256;
     const int c = e / (HP * WP), r = (e / WP) % HP, q = e % WP;
     const int yy = y0 - 1 + r, xx = x0 - 1 + q;
-    float v = 0.f;
-    if (yy >= 0 && yy < h && xx >= 0 && xx < w)
-      v = a.img[((long long)c * a.img_h + (g.gy[t] + yy)) * a.img_w + (g.gx[t] + xx)];
-    ip[e] = v;
+    v[i] = 0.f;
+    if (e < 3 * HP * WP && yy >= 0 && yy < h && xx >= 0 && xx < w)
+      v[i] = a.img[((long long)c * a.img_h + (g.gy[t] + yy)) * a.img_w + (g.gx[t] + xx)];
   }
-  __syncthreads();
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_conv_img(ConvArgs a, Batch g) {
+  constexpr int PH = 8, PW = 32, BM = 256, BN = 64, TM = 2, TN = 2, KP = 32;
+  constexpr int HP = PH + 2, WP = PW + 2;               // image patch with its 1-pixel halo
+  constexpr int RS = KP + 16 / (int)sizeof(T);         // LDS row stride (elements), 16 B pad
+  // im2col rows, then (reused) the two-pass FP32 epilogue tile; weights and the image
+  // patch live apart so they survive the epilogue
+  constexpr int SMEM = BM * RS * (int)sizeof(T) > BM * (32 + 8) * 4 ? BM * RS * (int)sizeof(T)
+                                                                   : BM * (32 + 8) * 4;
+  static_assert(3 * HP * WP <= 4 * 256, "image patch exceeds four values per thread");
+  __shared__ __attribute__((aligned(16))) unsigned char smem[SMEM];
+  __shared__ __attribute__((aligned(16))) T Bs[BN * RS];
+  __shared__ __attribute__((aligned(16))) float ip[3 * HP * WP];
+  T *const As = (T *)smem;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int l32 = lane & 31, half = lane >> 5;
+  const int npatch = g.pfx[g.n];
   {
-    const int ty = tid / PW, tx = tid % PW;
-    T row[KP];
-#pragma unroll
-    for (int k = 0; k < KP; ++k) {
-      float v = 0.f;
-      if (k < 27) {
-        const int tap = k / 3, c = k - 3 * (k / 3);
-        v = ip[(c * HP + ty + tap / 3) * WP + tx + tap % 3];
-      }
-      row[k] = from_f<T>(v);
-    }
-#pragma unroll
-    for (int k = 0; k < KP; ++k) As[tid * RS + k] = row[k];
     // weight operand: packed [KP / CK][1][64][CK]; row n of B = the 32 k-values of n
     const T *wp = (const T *)a.wp;
     constexpr int CK = Tr<T>::CK;
@@ -749,57 +756,89 @@ __global__ __launch_bounds__(256) void k_conv_img(ConvArgs a, Batch g) {
       Bs[n * RS + k] = wp[((long long)(k / CK) * a.cout_pad + n) * CK + (k % CK)];
     }
   }
-  __syncthreads();
-  f32x16 acc[TM][TN];
+  float iv[4];
+  if (blockIdx.x < npatch) img_patch_load<T>(iv, a, g, blockIdx.x, tid);
+#pragma unroll 1
+  for (int patch = blockIdx.x; patch < npatch; patch += gridDim.x) {
+    const int t = find_tile(g, patch);
+    const int lb = patch - g.pfx[t];
+    const int h = g.h[t], w = g.w[t];
+    const int nbx = (w + PW - 1) / PW;
+    const int y0 = (lb / nbx) * PH, x0 = (lb % nbx) * PW;
+    const long long slot = g.slot[t];
+    __syncthreads();   // the previous patch's epilogue is done with smem and ip
 #pragma unroll
-  for (int i = 0; i < TM; ++i)
+    for (int i = 0; i < 4; ++i)
+      if (tid + i * 256 < 3 * HP * WP) ip[tid + i * 256] = iv[i];
+    __syncthreads();
+    if (patch + (int)gridDim.x < npatch) img_patch_load<T>(iv, a, g, patch + gridDim.x, tid);
+    {
+      const int ty = tid / PW, tx = tid % PW;
+      T row[KP];
 #pragma unroll
-    for (int j = 0; j < TN; ++j)
+      for (int k = 0; k < KP; ++k) {
+        float v = 0.f;
+        if (k < 27) {
+          const int tap = k / 3, c = k - 3 * (k / 3);
+          v = ip[(c * HP + ty + tap / 3) * WP + tx + tap % 3];
+        }
+        row[k] = from_f<T>(v);
+      }
 #pragma unroll
-      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
-  // lane half g covers k in [16 g, 16 g + 16)
-  typename Mma<T>::Frag af[TM], bfr[TN];
-  if constexpr (sizeof(T) == 2) {
-#pragma unroll
-    for (int tm = 0; tm < TM; ++tm) {
-      const T *p = &As[(wave * 64 + tm * 32 + l32) * RS + half * 16];
-      af[tm].v[0] = *(const bf16x8 *)p;
-      af[tm].v[1] = *(const bf16x8 *)(p + 8);
+      for (int k = 0; k < KP; ++k) As[tid * RS + k] = row[k];
     }
+    __syncthreads();
+    f32x16 acc[TM][TN];
 #pragma unroll
-    for (int tn = 0; tn < TN; ++tn) {
-      const T *p = &Bs[(tn * 32 + l32) * RS + half * 16];
-      bfr[tn].v[0] = *(const bf16x8 *)p;
-      bfr[tn].v[1] = *(const bf16x8 *)(p + 8);
-    }
+    for (int i = 0; i < TM; ++i)
 #pragma unroll
-    for (int tm = 0; tm < TM; ++tm)
+      for (int j = 0; j < TN; ++j)
 #pragma unroll
-      for (int tn = 0; tn < TN; ++tn) Mma<T>::mma(acc[tm][tn], af[tm], bfr[tn]);
-  } else {
-#pragma unroll
-    for (int hh = 0; hh < 2; ++hh) {
+        for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+    // lane half g covers k in [16 g, 16 g + 16)
+    typename Mma<T>::Frag af[TM], bfr[TN];
+    if constexpr (sizeof(T) == 2) {
 #pragma unroll
       for (int tm = 0; tm < TM; ++tm) {
-        const T *p = &As[(wave * 64 + tm * 32 + l32) * RS + half * 16 + hh * 8];
-        af[tm].v[0] = *(const f32x4 *)p;
-        af[tm].v[1] = *(const f32x4 *)(p + 4);
+        const T *p = &As[(wave * 64 + tm * 32 + l32) * RS + half * 16];
+        af[tm].v[0] = *(const bf16x8 *)p;
+        af[tm].v[1] = *(const bf16x8 *)(p + 8);
       }
 #pragma unroll
       for (int tn = 0; tn < TN; ++tn) {
-        const T *p = &Bs[(tn * 32 + l32) * RS + half * 16 + hh * 8];
-        bfr[tn].v[0] = *(const f32x4 *)p;
-        bfr[tn].v[1] = *(const f32x4 *)(p + 4);
+        const T *p = &Bs[(tn * 32 + l32) * RS + half * 16];
+        bfr[tn].v[0] = *(const bf16x8 *)p;
+        bfr[tn].v[1] = *(const bf16x8 *)(p + 8);
       }
 #pragma unroll
       for (int tm = 0; tm < TM; ++tm)
 #pragma unroll
         for (int tn = 0; tn < TN; ++tn) Mma<T>::mma(acc[tm][tn], af[tm], bfr[tn]);
+    } else {
+#pragma unroll
+      for (int hh = 0; hh < 2; ++hh) {
+#pragma unroll
+        for (int tm = 0; tm < TM; ++tm) {
+          const T *p = &As[(wave * 64 + tm * 32 + l32) * RS + half * 16 + hh * 8];
+          af[tm].v[0] = *(const f32x4 *)p;
+          af[tm].v[1] = *(const f32x4 *)(p + 4);
+        }
+#pragma unroll
+        for (int tn = 0; tn < TN; ++tn) {
+          const T *p = &Bs[(tn * 32 + l32) * RS + half * 16 + hh * 8];
+          bfr[tn].v[0] = *(const f32x4 *)p;
+          bfr[tn].v[1] = *(const f32x4 *)(p + 4);
+        }
+#pragma unroll
+        for (int tm = 0; tm < TM; ++tm)
+#pragma unroll
+          for (int tn = 0; tn < TN; ++tn) Mma<T>::mma(acc[tm][tn], af[tm], bfr[tn]);
+      }
     }
+    __syncthreads();   // the epilogue reuses the im2col buffer
+    conv_epilogue<T, BN, 4, 1, PH, EPI_FWD, SMEM>(acc, (T *)smem, a, g, t, slot, y0, x0, h, w, 0, tid, wave, 0,
+                                                  l32, half);
   }
-  __syncthreads();   // the epilogue reuses the operand buffers
-  conv_epilogue<T, BN, 4, 1, PH, EPI_FWD, SMEM>(acc, (T *)smem, a, g, t, slot, y0, x0, h, w, 0, tid, wave, 0,
-                                                l32, half);
 }
 
 template <typename T, int PH, int BN, int WM, int WN, int IN, int EPI, bool SEG2>
@@ -859,7 +898,12 @@ static hipError_t conv_dispatch(int in_mode, int epi, const ConvArgs &a, const B
       if (a.cout != 64 || a.rc) return hipErrorInvalidValue;
       const int nblk = g.pfx[g.n];
       if (nblk == 0) return hipSuccess;
-      hipLaunchKernelGGL(k_conv_img<T>, dim3(nblk), dim3(256), 0, s, a, g);
+      int dev = 0, ncu = 0;
+      hipError_t e = hipGetDevice(&dev);
+      if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+      if (e != hipSuccess) return e;
+      const int grid = std::min(nblk, kImgBlocksPerCU * ncu);
+      hipLaunchKernelGGL(k_conv_img<T>, dim3(grid), dim3(256), 0, s, a, g);
       return hipGetLastError();
     }
     if (in_mode != IN_NHWC) return hipErrorInvalidValue;
