@@ -1125,15 +1125,24 @@ __global__ __launch_bounds__(256) void k_gram(const T *act, long long act_ss, in
 // BF16 Gram partials: same chunks and output layout as k_gram, on bf16 MFMA.  A stage of
 // 64 owned pixels is written channel-major into LDS (row = channel, 64 pixels + pad), so
 // that each lane's operand is 8 consecutive pixels of one channel; products are exact in
-// FP32 and accumulate in FP32 within the chunk.  Block CB x CB of the Gram per workgroup,
-// 4 waves in 2 x 2.
+// FP32 and accumulate in FP32 within the chunk.  Stages are double-buffered (one barrier
+// per stage, the next stage's loads in registers during the MFMAs).  Block CB x CB of
+// the Gram per workgroup, 4 waves in 2 x 2.
 template <int CB>
 __global__ __launch_bounds__(256) void k_gram_bf16(const bf16 *act, long long act_ss, int C,
                                                    Batch g, float *part, long long part_ss) {
   constexpr int SP = 64, RS = SP + 8;                  // pixels per stage, LDS row stride
   constexpr int TB = CB / 64;                           // 32x32 blocks per wave per dim
-  __shared__ __attribute__((aligned(16))) bf16 At[CB * RS];
-  __shared__ __attribute__((aligned(16))) bf16 Bt[CB * RS];
+  // stage loads: item u of an operand = (pixel pair u % 32, channel group u / 32), two
+  // 16-byte loads; lanes 0-31 of a wave cover one group's 64 pixels, lanes 32-63 the next
+  // group, so the packed 32-bit channel-major writes hit 64 distinct banks
+  constexpr int NI = (SP / 2) * (CB / 8);               // items per operand per stage
+  constexpr int PT = 2 * NI / 256;                      // items per thread (both operands)
+  static_assert((2 * NI) % 256 == 0 && SP == 64, "stage items per thread");
+  // double-buffered channel-major stages: the next stage's loads are in registers while
+  // the MFMAs of the current one run
+  __shared__ __attribute__((aligned(16))) bf16 At[2][CB * RS];
+  __shared__ __attribute__((aligned(16))) bf16 Bt[2][CB * RS];
   const int t = find_tile(g, blockIdx.x);
   const int k = blockIdx.x - g.pfx[t];
   const int nb = C / CB;
@@ -1161,31 +1170,51 @@ __global__ __launch_bounds__(256) void k_gram_bf16(const bf16 *act, long long ac
     for (int j = 0; j < TB; ++j)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
-  constexpr int NV = SP * CB / 8;                      // 16-byte loads per operand per stage
-  for (int qs = q0; qs < q1; qs += SP) {
-    __syncthreads();
-    for (int v = tid; v < NV * (diag ? 1 : 2); v += 256) {
-      const int op = v >= NV, vv = v - op * NV;
-      const int pl = vv / (CB / 8), cg = vv - pl * (CB / 8);
-      const int q = qs + pl;
-      Vec<bf16> d;
-      d.u = make_uint4(0u, 0u, 0u, 0u);
-      if (q < q1) {
-        const int y = r0 + q / ow, x = c0 + q % ow;
-        d.u = *(const uint4 *)(b + ((long long)y * w + x) * C + (op ? bj : bi) * CB + cg * 8);
-      }
-      bf16 *dst = op ? Bt : At;
+  Vec<bf16> pre[PT][2];
+  auto load_stage = [&](int qs) __attribute__((always_inline)) {
 #pragma unroll
-      for (int j = 0; j < 8; ++j) dst[(cg * 8 + j) * RS + pl] = d.e[j];
+    for (int i = 0; i < PT; ++i) {
+      const int v = tid + i * 256;
+      const int op = v >= NI, u = v - op * NI;
+      const int pp = u & 31, cg = u >> 5;
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const int q = qs + 2 * pp + e;
+        pre[i][e].u = make_uint4(0u, 0u, 0u, 0u);
+        if (q < q1 && (!op || !diag)) {
+          const int y = r0 + q / ow, x = c0 + q % ow;
+          pre[i][e].u = *(const uint4 *)(b + ((long long)y * w + x) * C + (op ? bj : bi) * CB + cg * 8);
+        }
+      }
+    }
+  };
+  load_stage(q0);
+  int buf = 0;
+  for (int qs = q0; qs < q1; qs += SP, buf ^= 1) {
+#pragma unroll
+    for (int i = 0; i < PT; ++i) {
+      const int v = tid + i * 256;
+      const int op = v >= NI, u = v - op * NI;
+      const int pp = u & 31, cg = u >> 5;
+      if (op && diag) continue;
+      unsigned *dst = (unsigned *)(op ? Bt[buf] : At[buf]);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const unsigned lo = __builtin_bit_cast(unsigned short, pre[i][0].e[j]);
+        const unsigned hi = __builtin_bit_cast(unsigned short, pre[i][1].e[j]);
+        dst[((cg * 8 + j) * RS + 2 * pp) >> 1] = lo | (hi << 16);
+      }
     }
     __syncthreads();
-    const bf16 *Bsrc = diag ? At : Bt;
+    if (qs + SP < q1) load_stage(qs + SP);
+    const bf16 *Asrc = At[buf];
+    const bf16 *Bsrc = diag ? At[buf] : Bt[buf];
 #pragma unroll
     for (int ks = 0; ks < SP / 16; ++ks) {
       bf16x8 fa[TB], fb[TB];
 #pragma unroll
       for (int i = 0; i < TB; ++i)
-        fa[i] = *(const bf16x8 *)(&At[(wi * 32 * TB + i * 32 + l32) * RS + ks * 16 + half * 8]);
+        fa[i] = *(const bf16x8 *)(&Asrc[(wi * 32 * TB + i * 32 + l32) * RS + ks * 16 + half * 8]);
 #pragma unroll
       for (int j = 0; j < TB; ++j)
         fb[j] = *(const bf16x8 *)(&Bsrc[(wj * 32 * TB + j * 32 + l32) * RS + ks * 16 + half * 8]);
