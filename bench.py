@@ -8,7 +8,9 @@ conv1_1..conv5_1 with seeded He-normal weights, style layers relu{1..5}_1 with
 w = 1/5, content relu4_2 with alpha = 1, tiles of 1024 px with the exact
 receptive-field margin 155 (48 tiles).  The style Grams and content features are
 computed once, untimed; each timed step is nst_loss_grad(STEP1 | STEP2) with all
-inputs resident in HBM.
+inputs resident in HBM.  When the workspace (--ws-gib) holds every tile, Step 2 runs the
+backward on the activations Step 1 left resident; --recompute sizes it for tile batches
+so that Step 2 recomputes each tile's forward as Algorithm 1 prints it.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -24,8 +26,9 @@ sys.path.insert(0, ROOT)
 METRIC = "Mpixel/s per style+content loss+grad eval (VGG-19); BF16 vs FP32 at stated grad error"
 PEAK_TFLOPS = {"bf16": 2500.0, "fp32": 157.3}
 HBM_GBS = 8000.0
-# algorithmic FLOPs of one evaluation per image pixel: two forwards, one data
-# gradient, the style Grams and the style residual products (full VGG-19 prefix)
+# algorithmic FLOPs of one evaluation per image pixel as Algorithm 1 prints it: two
+# forwards, one data gradient, the style Grams and the style residual products (full
+# VGG-19 prefix); with resident activations one of the two forwards is not executed
 FLOP_PER_PX = 2 * 722304 + 722304 + 2 * 34816
 
 
@@ -47,9 +50,10 @@ def make_inputs(args):
 
 def run_precision(prec, steps, warmup, args, x, c, s, ws, bs, profile):
     import torch
-    from paper_2212_13459_amd import Context
+    from paper_2212_13459_amd import Context, plan, vgg19_desc, workspace_bytes
     dev = torch.device("cuda", 0)
-    nst = Context(ws, bs, prec, tile_batch=args.tile_batch, ws_limit=int(args.ws_gib * (1 << 30)))
+    nst = Context(ws, bs, prec, tile_batch=args.tile_batch, ws_limit=int(args.ws_gib * (1 << 30)),
+                  retain=not args.recompute)
     xd = torch.from_numpy(x).to(dev)
     gt = nst.style_grams(torch.from_numpy(s).to(dev), args.T, args.m)
     fc = nst.content_feats(torch.from_numpy(c).to(dev), args.T, args.m)
@@ -57,7 +61,11 @@ def run_precision(prec, steps, warmup, args, x, c, s, ws, bs, profile):
     gx = torch.empty_like(gt)
     grad = torch.empty_like(xd)
     torch.cuda.synchronize()
-    log(f"[bench] {prec}: targets ready, workspace {nst.workspace(args.H, args.W, args.T, args.m).numel() / 2**30:.1f} GiB")
+    nt = len(plan(vgg19_desc(), args.H, args.W, args.T, args.m))
+    wsb = nst.workspace(args.H, args.W, args.T, args.m).numel()
+    resident = wsb >= workspace_bytes(vgg19_desc(), prec, args.H, args.W, args.T, args.m, nt)
+    log(f"[bench] {prec}: targets ready, workspace {wsb / 2**30:.1f} GiB, "
+        f"{'every tile resident (Step 2 reuses Step 1 activations)' if resident else 'tile batches (Step 2 recomputes)'}")
     for i in range(warmup):
         nst.loss_grad(xd, gt, fc, w_style, 1.0, args.T, args.m, grams_x=gx, grad=grad, want_energy=False)
         torch.cuda.synchronize()
@@ -76,7 +84,8 @@ def run_precision(prec, steps, warmup, args, x, c, s, ws, bs, profile):
         nst.profile(False)
     energy, _, _ = nst.loss_grad(xd, gt, fc, w_style, 1.0, args.T, args.m, grams_x=gx, grad=grad)
     log(f"[bench] {prec}: {steps} steps, {dt * 1e3:.1f} ms/step, E={energy[0]:.6e}")
-    out = dict(ms=dt * 1e3, stats=stats, energy=energy, grad_norm=float(grad.double().norm()))
+    out = dict(ms=dt * 1e3, stats=stats, energy=energy, grad_norm=float(grad.double().norm()),
+               step2="reuses Step 1 activations" if resident else "recomputes the forward per tile batch")
     del nst, xd, gt, fc, gx, grad
     torch.cuda.empty_cache()
     return out
@@ -153,6 +162,9 @@ def main():
     ap.add_argument("--ws-gib", type=float, default=120.0)
     ap.add_argument("--cpu-sample", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--recompute", action="store_true",
+                    help="size the workspace for a tile batch, so that Step 2 recomputes each tile's "
+                         "forward (Algorithm 1 as printed) instead of reusing Step 1's resident activations")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first launch a plain copy (negation) kernel of this many MiB three times, "
                          "as the reference for FETCH_SIZE / WRITE_SIZE counters")
@@ -190,7 +202,7 @@ def main():
         "config": {"workload": f"loss+grad x {args.H}x{args.W}, style {args.Hs}x{args.Ws}, "
                                f"tiles {args.T} px margin {args.m} ({n_tiles} tiles), VGG-19 conv1_1..conv5_1",
                    "H": args.H, "W": args.W, "style_H": args.Hs, "style_W": args.Ws, "T": args.T, "m": args.m,
-                   "tiles": n_tiles, "style_weight": 0.2, "alpha": 1.0},
+                   "tiles": n_tiles, "style_weight": 0.2, "alpha": 1.0, "step2": main_res["step2"]},
         "roofline": roofline(args.precision, main_res["stats"], args.steps),
         "effective_mfma_frac": round(FLOP_PER_PX * args.H * args.W / (ms * 1e-3) / 1e12 / peak, 4),
         "kernels": [{k: (round(v, 4) if isinstance(v, float) else v) for k, v in st.items()}
@@ -200,7 +212,7 @@ def main():
     if args.fp32_steps > 0 and args.precision != "fp32":
         r32 = run_precision("fp32", args.fp32_steps, 1, args, x, c, s, ws, bs, profile=False)
         result["fp32"] = {"value": round(args.H * args.W / (r32["ms"] * 1e-3) / 1e6, 3),
-                          "ms_per_step": round(r32["ms"], 3),
+                          "ms_per_step": round(r32["ms"], 3), "step2": r32["step2"],
                           "speedup_of_bf16": round(r32["ms"] / ms, 3),
                           "energy_rel_diff_bf16_vs_fp32": abs(main_res["energy"][0] - r32["energy"][0]) / abs(r32["energy"][0]),
                           "grad_norm_rel_diff": abs(main_res["grad_norm"] - r32["grad_norm"]) / r32["grad_norm"]}

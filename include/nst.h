@@ -112,7 +112,11 @@ int nst_plan(const nst_net_desc *net, int H, int W, int T, int m,
              nst_tile *out, int cap, int *n_tiles);
 
 /* Device workspace needed to process `tile_batch` tiles of the plan at once with the given
- * precision; the run calls use the largest batch that fits in what they are given.  Host only. */
+ * precision; the run calls use the largest batch that fits in what they are given.  With
+ * tile_batch >= the plan's tile count the workspace holds every tile's activations, and
+ * nst_loss_grad with NST_STEP1 | NST_STEP2 then runs Step 2's backward on the activations
+ * its Step 1 left resident instead of recomputing them (same results, bit for bit).
+ * Host only. */
 int nst_workspace_bytes(const nst_net_desc *net, int precision, int H, int W, int T, int m,
                         int tile_batch, size_t *bytes);
 

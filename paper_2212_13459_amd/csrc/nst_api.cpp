@@ -140,7 +140,8 @@ constexpr size_t kAlign = 256;
 size_t al(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-  int batch = 0;
+  int batch = 0;                // tiles per launch
+  int nslots = 0;               // tile slots (batch, or every tile of the plan)
   size_t total = 0;
   int hmax = 0, wmax = 0;
   int lh[NST_MAX_CONV] = {}, lw[NST_MAX_CONV] = {};
@@ -167,12 +168,14 @@ int max_window_ok(const Geom &g, const Layout &L) {
   return NST_OK;
 }
 
-// Layout for a given batch size.  Independent of which entry point runs so that one
-// workspace size serves every call on the same (H, W, T, m).
+// Layout for a launch batch and a number of tile slots (the batch, or every tile of the
+// plan so that activations stay resident from Step 1 to Step 2).  Independent of which
+// entry point runs so that one workspace size serves every call on the same (H, W, T, m).
 void make_layout(const Geom &g, int precision, const std::vector<nst_tile> &tiles, int batch,
-                 Layout &L) {
+                 int nslots, Layout &L) {
   L = Layout();
   L.batch = batch;
+  L.nslots = nslots;
   L.es = elem_size(precision);
   for (const nst_tile &t : tiles) {
     L.hmax = std::max(L.hmax, t.ey1 - t.ey0);
@@ -251,7 +254,14 @@ void make_layout(const Geom &g, int precision, const std::vector<nst_tile> &tile
     so = al(so + (size_t)L.gchunks[k] * C * C * 4);
   }
   L.slot_bytes = so;
-  L.total = L.slots + (size_t)batch * L.slot_bytes;
+  L.total = L.slots + (size_t)nslots * L.slot_bytes;
+}
+
+// Launch batch when every tile has a slot: the fewest launches of at most kMaxBatch
+// tiles, evenly filled.
+int balanced_batch(int nt) {
+  const int nb = (nt + kMaxBatch - 1) / kMaxBatch;
+  return (nt + nb - 1) / nb;
 }
 
 // -------------------------------------------------------------- bf16 pack ----------
@@ -405,8 +415,14 @@ int nst_workspace_bytes(const nst_net_desc *net, int precision, int H, int W, in
   if (tile_batch < 1) return NST_EINVAL;
   std::vector<nst_tile> tiles;
   build_plan(g, H, W, T, m, tiles);
+  const int nt = (int)tiles.size();
   Layout L;
-  make_layout(g, precision, tiles, std::min({tile_batch, (int)tiles.size(), kMaxBatch}), L);
+  if (tile_batch >= nt)
+    make_layout(g, precision, tiles, balanced_batch(nt), nt, L);
+  else {
+    const int b = std::min(tile_batch, kMaxBatch);
+    make_layout(g, precision, tiles, b, b, L);
+  }
   if ((st = max_window_ok(g, L)) != NST_OK) return st;
   *bytes = L.total;
   return NST_OK;
@@ -503,6 +519,7 @@ struct Runner {
   nst_ctx *c;
   const Geom &g;
   Layout L;
+  bool retain = false;          // every tile has its own slot (activations stay resident)
   std::vector<nst_tile> tiles;
   char *ws;
   hipStream_t s;
@@ -578,7 +595,7 @@ struct Runner {
       b.a1[k] = t.own[i][1] - b.gy[k];
       b.a2[k] = t.own[i][2] - b.gx[k];
       b.a3[k] = t.own[i][3] - b.gx[k];
-      b.slot[k] = k;
+      b.slot[k] = retain ? first + k : k;
     }
     return b;
   }
@@ -797,13 +814,21 @@ int setup(Runner &R, nst_ctx *ctx, int H, int W, int T, int m, void *ws, size_t 
   build_plan(ctx->g, H, W, T, m, R.tiles);
   const int nt = (int)R.tiles.size();
   Layout L1;
-  make_layout(ctx->g, ctx->prec, R.tiles, 1, L1);
+  make_layout(ctx->g, ctx->prec, R.tiles, 1, 1, L1);
   if ((st = max_window_ok(ctx->g, L1)) != NST_OK) return st;
   if (ws_bytes < L1.total) return NST_EWORKSPACE;
+  // a slot per tile if it fits: Step 2 then reuses Step 1's activations
+  Layout La;
+  make_layout(ctx->g, ctx->prec, R.tiles, balanced_batch(nt), nt, La);
+  if (La.total <= ws_bytes) {
+    R.L = La;
+    R.retain = true;
+    return NST_OK;
+  }
   int best = 1;
   for (int b = std::min(nt, kMaxBatch); b > 1; --b) {
     Layout Lb;
-    make_layout(ctx->g, ctx->prec, R.tiles, b, Lb);
+    make_layout(ctx->g, ctx->prec, R.tiles, b, b, Lb);
     if (Lb.total <= ws_bytes) {
       best = b;
       break;
@@ -812,11 +837,13 @@ int setup(Runner &R, nst_ctx *ctx, int H, int W, int T, int m, void *ws, size_t 
   // balance: same number of batches, evenly filled
   const int nb = (nt + best - 1) / best;
   const int bal = (nt + nb - 1) / nb;
-  make_layout(ctx->g, ctx->prec, R.tiles, bal, R.L);
+  make_layout(ctx->g, ctx->prec, R.tiles, bal, bal, R.L);
   return NST_OK;
 }
 
-int step1(Runner &R, const float *x, const float *fc) {
+// keep: also store full-resolution activations of pooled layers (for a Step 2 that
+// reuses this pass's activations)
+int step1(Runner &R, const float *x, const float *fc, bool keep) {
   const Geom &g = R.g;
   HIPCHK(launch_fill_f64(R.gl<double>(R.L.g_gacc), (R.L.g_dt - R.L.g_gacc) / 8, 0.0, R.s));
   HIPCHK(launch_fill_f64(R.gl<double>(R.L.g_ec), 1, 0.0, R.s));
@@ -826,7 +853,7 @@ int step1(Runner &R, const float *x, const float *fc) {
   const int nt = (int)R.tiles.size();
   for (int first = 0; first < nt; first += R.L.batch) {
     const int n = std::min(R.L.batch, nt - first);
-    int st = R.forward(first, n, upto, x, fc, false);
+    int st = R.forward(first, n, upto, x, fc, keep);
     if (st != NST_OK) return st;
     if ((st = R.grams(first, n)) != NST_OK) return st;
     if (fc && (st = R.content_energy(first, n)) != NST_OK) return st;
@@ -898,7 +925,7 @@ int nst_style_grams(nst_ctx *ctx, const float *s, int H, int W, int T, int m, do
   Runner R(ctx);
   int st = setup(R, ctx, H, W, T, m, ws, ws_bytes, stream, 0);
   if (st != NST_OK) return st;
-  if ((st = step1(R, s, nullptr)) != NST_OK) return st;
+  if ((st = step1(R, s, nullptr, false)) != NST_OK) return st;
   return normalize(R, grams);
 }
 
@@ -961,7 +988,7 @@ int nst_loss_grad(nst_ctx *ctx, const float *x, int H, int W, const double *targ
   }
 
   if (s1) {
-    if ((st = step1(R, x, fc)) != NST_OK) return st;
+    if ((st = step1(R, x, fc, R.retain && s2)) != NST_OK) return st;
     if ((st = normalize(R, grams_x)) != NST_OK) return st;
   } else {
     HIPCHK(launch_fill_f64(R.gl<double>(R.L.g_ec), 1, 0.0, R.s));
@@ -973,7 +1000,9 @@ int nst_loss_grad(nst_ctx *ctx, const float *x, int H, int W, const double *targ
     const int nt = (int)R.tiles.size();
     for (int first = 0; first < nt; first += R.L.batch) {
       const int n = std::min(R.L.batch, nt - first);
-      if ((st = R.forward(first, n, g.top, x, fc, true)) != NST_OK) return st;
+      // Step 1 of this call left every tile's activations (and content difference) in its
+      // slot when each tile has one; otherwise Step 2 recomputes them (Algorithm 1)
+      if (!(s1 && R.retain) && (st = R.forward(first, n, g.top, x, fc, true)) != NST_OK) return st;
       if (!s1 && fc && (st = R.content_energy(first, n)) != NST_OK) return st;
       if ((st = R.backward(first, n, (float)(2.0 * alpha), use_c, grad)) != NST_OK) return st;
     }

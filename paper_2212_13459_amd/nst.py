@@ -71,7 +71,7 @@ class Context:
 
     def __init__(self, weights, biases=None, precision: str = "fp32", desc: NetDesc | None = None,
                  tiny: bool = False, with_content: bool = True, ws_limit: int = 96 << 30,
-                 tile_batch: int = 32):
+                 tile_batch: int = 32, retain: bool = True):
         self.desc = desc if desc is not None else vgg19_desc(tiny, with_content)
         self.convs, self.style, self.content = desc_info(self.desc)
         self.precision = precision
@@ -88,6 +88,7 @@ class Context:
         self._h = h
         self.ws_limit = ws_limit
         self.tile_batch = tile_batch
+        self.retain = retain
         self._ws = {}
         strides, s = [], 1
         for i in range(n):
@@ -132,13 +133,19 @@ class Context:
         return out
 
     def workspace(self, H, W, T, m):
+        """Device workspace: a slot per tile when retain is set and that fits in ws_limit
+        (Step 2 then reuses Step 1's activations), else the largest tile batch that fits
+        (at most tile_batch, below the tile count)."""
         key = (H, W, T, m)
         if key not in self._ws:
-            b = min(self.tile_batch, len(plan(self.desc, H, W, T, m)))
-            nbytes = workspace_bytes(self.desc, self.precision, H, W, T, m, b)
-            while b > 1 and nbytes > self.ws_limit:
-                b -= 1
+            nt = len(plan(self.desc, H, W, T, m))
+            nbytes = workspace_bytes(self.desc, self.precision, H, W, T, m, nt)
+            if not self.retain or nbytes > self.ws_limit:
+                b = min(self.tile_batch, nt - 1) if nt > 1 else 1
                 nbytes = workspace_bytes(self.desc, self.precision, H, W, T, m, b)
+                while b > 1 and nbytes > self.ws_limit:
+                    b -= 1
+                    nbytes = workspace_bytes(self.desc, self.precision, H, W, T, m, b)
             self._ws = {key: torch.empty(nbytes, dtype=torch.uint8, device=self.device)}
         return self._ws[key]
 

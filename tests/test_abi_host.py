@@ -119,6 +119,25 @@ def test_workspace_sizes(L):
     assert L.nst_workspace_bytes(byref(d), 0, 64, 64, 64, 0, 0, byref(out)) == -1   # batch < 1
 
 
+def test_workspace_with_a_slot_per_tile():
+    """tile_batch >= the tile count sizes one slot per tile (activations resident from
+    Step 1 to Step 2): the same size for any such tile_batch, about nt slots."""
+    from paper_2212_13459_amd.nst import plan, vgg19_desc, workspace_bytes
+    d = vgg19_desc()
+    nt = len(plan(d, 6048, 8064, 1024, 155))
+    assert nt == 48
+    all_tiles = workspace_bytes(d, "bf16", 6048, 8064, 1024, 155, nt)
+    assert all_tiles == workspace_bytes(d, "bf16", 6048, 8064, 1024, 155, nt + 7)
+    one = workspace_bytes(d, "bf16", 6048, 8064, 1024, 155, 1)
+    two = workspace_bytes(d, "bf16", 6048, 8064, 1024, 155, 2)
+    step = two - one          # one slot plus one tile's Gram-sum scratch
+    assert (nt - 1) * step < all_tiles < nt * step
+    # fewer tiles than the launch limit: the batch already holds every tile
+    n_small = len(plan(d, 200, 328, 96, 155))
+    assert workspace_bytes(d, "bf16", 200, 328, 96, 155, n_small) == \
+        workspace_bytes(d, "bf16", 200, 328, 96, 155, 100)
+
+
 def test_run_entry_points_validate_before_touching_the_device(L):
     assert L.nst_style_grams(None, None, 64, 64, 64, 0, None, None, 0, None) == -1
     assert L.nst_content_feats(None, None, 64, 64, 64, 0, None, None, 0, None) == -1

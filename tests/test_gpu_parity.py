@@ -206,6 +206,28 @@ def test_deterministic(prec):
     assert e1 == e2 and torch.equal(g1, g2) and torch.equal(d1, d2)
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_step2_reuse_equals_recompute(prec):
+    """A workspace with a slot per tile (Step 2 reuses the activations Step 1 left
+    resident) and one with two tile slots (Step 2 recomputes them batch by batch, as in
+    Algorithm 1) give bit-identical energies, Grams of x and gradients (12 tiles)."""
+    from paper_2212_13459_amd import Context, plan
+    k = case(*RAGGED)
+    resident = ctx("full", prec)
+    recompute = Context(k["ws"], k["bs"], prec, tile_batch=2, retain=False)
+    assert len(plan(resident.desc, k["H"], k["W"], 96, 155)) == 12
+    g_t, f_c = oracle_targets(*RAGGED)
+    gt_d = cuda(flat_grams(g_t), torch.float64)
+    fc_d = cuda(fc_hwc(f_c))
+    x = cuda(k["x"])
+    e1, g1, d1 = resident.loss_grad(x, gt_d, fc_d, W5, 1.0, 96, 155)
+    g1, d1 = g1.clone(), d1.clone()
+    e2, g2, d2 = recompute.loss_grad(x, gt_d, fc_d, W5, 1.0, 96, 155)
+    torch.cuda.synchronize()
+    assert resident.workspace(k["H"], k["W"], 96, 155).numel() > recompute.workspace(k["H"], k["W"], 96, 155).numel()
+    assert e1 == e2 and torch.equal(g1, g2) and torch.equal(d1, d2)
+
+
 def test_zero_energy_when_x_c_s_coincide_fp32():
     k = case(*RAGGED)
     nst = ctx("full", "fp32")
