@@ -446,6 +446,13 @@ __device__ __attribute__((aligned(16))) unsigned kZeroRow[4] = {0u, 0u, 0u, 0u};
 
 typedef __attribute__((address_space(3))) void lds_void;
 
+// Workgroup barrier for the conv stage loops: waits for this wave's LDS reads and writes
+// (lgkmcnt 0), not for its global loads.  __syncthreads() (and an LDS-only fence, which
+// counts LDS DMA as pending LDS writes) would wait for every outstanding load, vmcnt 0;
+// here the stage code waits explicitly for the DMA that the next stage reads and leaves
+// later DMA (the next chunk's halo) in flight.  The asm is a compiler memory barrier.
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
 template <typename T, int NT, int ANVD, int AUNITS, int VEC>
 __device__ __forceinline__ void dma_a(T *__restrict__ dst, const T *base, const unsigned (&arel)[ANVD],
                                       unsigned okbits, int cin, int wv, int tid) {
@@ -495,12 +502,16 @@ __device__ __forceinline__ void stage_dma(f32x16 (&acc)[TM][TN], const T *__rest
                                           const unsigned (&arel)[ANVD], unsigned okbits, int cin,
                                           T *__restrict__ bdst, const T *wbase, const unsigned (&boff)[BNV],
                                           bool issue_b, bool issue_a, int wv, int tid) {
+  constexpr int NK = 2 * NTAP;
+  KFrag<TM, TN> f[2];
+  // the first k-step's fragment reads go out before the DMA instructions, whose issue then
+  // covers their latency (the DMA writes the other buffers); a single wait before the
+  // first MFMA follows
+  load_kstep<T, TM, TN, BN, CK, VEC>(f[0], A, B, pidx, toff0, 0, 0, bcol, half);
+  __builtin_amdgcn_sched_barrier(0);
   if (issue_b) dma_b<T, NT, BNV, VEC>(bdst, wbase, boff, wv);
   if (DA && issue_a) dma_a<T, NT, ANVD, AUNITS, VEC>(adst, abase, arel, okbits, cin, wv, tid);
   __builtin_amdgcn_sched_barrier(0);
-  constexpr int NK = 2 * NTAP;
-  KFrag<TM, TN> f[2];
-  load_kstep<T, TM, TN, BN, CK, VEC>(f[0], A, B, pidx, toff0, 0, 0, bcol, half);
   // the next k-step's NLD fragment reads are interleaved with the first MFMAs of this
   // k-step (R MFMAs, then one read), so they are in flight during the rest of it, the
   // LDS counter (4 bits) never tracks two k-steps of reads, and the only LDS wait of a
@@ -645,19 +656,19 @@ __global__ __launch_bounds__(WM * WN * 64) void k_conv3(ConvArgs a, Batch g) {
     stage_dma<T, TM, TN, BN, CK, VEC, 3, NT, ANVD, AUNITS, BNV, true, AMIN>(
         acc, Ac, Bx, pidx, 0, bcol, half, An, anext, arel, okbits, more ? a.cin : a.cin2, By,
         wp0 + (c * 9 + 3) * wrow, boff, true, more || seg, wv, tid);
-    __syncthreads();
+    lds_barrier();
     // filter row 1 (y); prefetch row 2 into x (the halo patch lands with it)
     stage_dma<T, TM, TN, BN, CK, VEC, 3, NT, ANVD, AUNITS, BNV, false, 0>(
         acc, Ac, By, pidx, WP, bcol, half, nullptr, nullptr, arel, okbits, 0, Bx, wp0 + (c * 9 + 6) * wrow, boff,
         true, false, wv, tid);
-    __syncthreads();
+    lds_barrier();
     // filter row 2 (x); prefetch the next chunk's row 0 (or segment 1's weights) into y
     if (seg) dma_boff<T, NT, BNV, BN, CK, VEC>(boff, 1, a.cout_pad, n0, tid);
     const T *wnext = more ? wp0 + (c + 1) * 9 * wrow : wp1;
     stage_dma<T, TM, TN, BN, CK, VEC, 3, NT, ANVD, AUNITS, BNV, false, 0>(
         acc, Ac, Bx, pidx, 2 * WP, bcol, half, nullptr, nullptr, arel, okbits, 0, By, wnext, boff, more || seg,
         false, wv, tid);
-    __syncthreads();
+    lds_barrier();
   }
   if constexpr (SEG2) {
     const T *abase1 = in1 + ((long long)by * w + bx) * a.cin2;
@@ -669,7 +680,7 @@ __global__ __launch_bounds__(WM * WN * 64) void k_conv3(ConvArgs a, Batch g) {
           acc, (ac & 1) ? A1 : A0, (st & 1) ? B1 : B0, pidx, WP + 1, bcol, half, (ac & 1) ? A0 : A1,
           abase1 + (c2 + 1) * CK, arel, okbits, a.cin2, (st & 1) ? B0 : B1, wp1 + (long long)(c2 + 1) * wrow,
           boff, more, more, wv, tid);
-      __syncthreads();
+      lds_barrier();
     }
   }
   if constexpr (EPI == EPI_STITCH) {
