@@ -308,12 +308,28 @@ constexpr int epi_passes(int bm, int wn, int tn, int smem_bytes) {
   return 0;
 }
 
+// Workgroup barrier for the conv kernels: waits for this wave's LDS reads and writes
+// (lgkmcnt 0), not for its global loads.  __syncthreads() (and an LDS-only fence, which
+// counts LDS DMA as pending LDS writes) would wait for every outstanding load, vmcnt 0;
+// the stage code waits explicitly for the DMA that the next stage reads and leaves later
+// DMA (the next chunk's halo) in flight, and the epilogue does not wait for its global
+// stores between passes.  The asm is a compiler memory barrier.
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
 // Conv epilogue through LDS (the caller's last barrier has released its stage buffers,
 // SMEM_BYTES of them at sm), in NPASS passes over the wave's TN column blocks: phase 1
 // writes the raw FP32 accumulators of the pass, phase 2 reads VEC consecutive channels of
-// one pixel and applies bias + ReLU (+ content difference) or content residual + ReLU
-// mask with 16-byte loads and stores.  The arithmetic per element is the same as
-// applying it to the accumulator directly.
+// one pixel with 16-byte LDS reads and applies bias + ReLU (+ content difference), or
+// content residual + ReLU mask, with 16-byte global loads and stores.  The arithmetic per
+// element is the same as applying it to the accumulator directly.
+//   A thread keeps the same VEC channels for the whole pass (NT is a multiple of the
+// CPR channel chunks of a pixel row).  The forward epilogue walks 2 x 2 pooling windows:
+// it rounds each of the window's four outputs once, stores them and, for a pooled layer,
+// the first maximum of the rounded values in row-major window order, as a separate
+// pooling pass would.  The backward epilogue walks pixels in groups of G whose loads
+// (residual, mask) are issued together, the first group before phase 1.  Addresses are a
+// per-pass base plus a 64-bit element offset (pixel index times cout: a whole-image
+// window can hold more than 2^31 elements).
 template <typename T, int BN, int WM, int WN, int PH, int EPI, int SMEM_BYTES>
 __device__ __forceinline__ void conv_epilogue(f32x16 (&acc)[PH * 32 / (WM * 32)][BN / (WN * 32)], T *sm,
                                               const ConvArgs &a, const Batch &g, int t, long long slot,
@@ -321,17 +337,85 @@ __device__ __forceinline__ void conv_epilogue(f32x16 (&acc)[PH * 32 / (WM * 32)]
                                               int l32, int half) {
   constexpr int PW = 32, BM = PH * PW, NT = WM * WN * 64;
   constexpr int TM = BM / (WM * 32), TN = BN / (WN * 32);
-  constexpr int VEC = 16 / sizeof(T);
+  constexpr int VEC = 16 / sizeof(T), NQ = VEC / 4;
   constexpr int NPASS = epi_passes(BM, WN, TN, SMEM_BYTES);
   constexpr int TNP = TN / NPASS, CW = TNP * 32, RSW = WN * CW + 8;
   constexpr int CPR = WN * CW / VEC;
-  static_assert((BM * CPR) % NT == 0, "epilogue tiling");
+  static_assert(NT % CPR == 0 && PH % 2 == 0, "epilogue tiling");
   typedef T TV __attribute__((ext_vector_type(VEC)));
   float *so = (float *)sm;
   const int cout = a.cout;
+  const int lc = (tid % CPR) * VEC, ib = tid / CPR;
+  // forward: windows q = ib + k QSTEP (k < NW); backward: pixels m = ib + i MSTEP (i < NIT)
+  constexpr int PWO = PW / 2, PO = (PH / 2) * PWO, QSTEP = NT / CPR, NW = PO * CPR / NT;
+  constexpr int MSTEP = NT / CPR, NIT = BM * CPR / NT;
+  static_assert((PO * CPR) % NT == 0 && (BM * CPR) % NT == 0, "epilogue items");
+  static_assert(MSTEP % PW == 0 || PW % MSTEP == 0, "epilogue pixel stride");
+  constexpr int GW = NW < 2 ? NW : 2;            // forward: windows per load group
+  constexpr int G = EPI == EPI_FWD ? 4 * GW : (NIT < 8 ? NIT : 8);
+  static_assert(NW % GW == 0 && NIT % G == 0, "epilogue groups");
+  const bool fwd_rc = EPI == EPI_FWD && a.rc != nullptr, bwd_rc = EPI != EPI_FWD && a.rc != nullptr;
+  const bool bwd_mask = EPI != EPI_FWD && a.mask != nullptr;
+  // local (row, column) of item j of group g0
+  auto item_fwd = [&](int k, int kk, int &ly, int &lx) __attribute__((always_inline)) {
+    const int q = ib + k * QSTEP;
+    ly = 2 * (q / PWO) + (kk >> 1);
+    lx = 2 * (q % PWO) + (kk & 1);
+  };
+  auto item_bwd = [&](int i, int &ly, int &lx) __attribute__((always_inline)) {
+    if constexpr (MSTEP % PW == 0) {
+      ly = ib / PW + i * (MSTEP / PW);
+      lx = ib % PW;
+    } else {
+      ly = i / (PW / MSTEP);
+      lx = ib + (i % (PW / MSTEP)) * MSTEP;   // ib < MSTEP
+    }
+  };
+  TV mk[G];
+  f32x4 dq[G][NQ];
+  // loads of group g0 at clamped addresses (every lane loads; items outside the window
+  // or past cout are not stored)
+  auto load_group = [&](int g0, int nc) __attribute__((always_inline)) {
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+      int ly, lx;
+      if constexpr (EPI == EPI_FWD)
+        item_fwd(g0 / 4 + j / 4, j % 4, ly, lx);
+      else
+        item_bwd(g0 + j, ly, lx);
+      const int py = min(y0 + ly, h - 1), px = min(x0 + lx, w - 1);
+      if (fwd_rc) {
+        const float *f = a.fc + ((long long)(g.gy[t] + py) * a.fc_w + (g.gx[t] + px)) * cout + nc;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) dq[j][q] = *(const f32x4 *)(f + 4 * q);
+      }
+      const long long po = (long long)(py * w + px) * cout;
+      if (bwd_rc) {
+        const float *rc = a.rc + slot * a.rc_ss + nc + po;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) dq[j][q] = *(const f32x4 *)(rc + 4 * q);
+      }
+      if (bwd_mask) mk[j] = *(const TV *)((const T *)a.mask + slot * a.mask_ss + nc + po);
+    }
+  };
 #pragma unroll
   for (int p = 0; p < NPASS; ++p) {
-    if (p > 0) __syncthreads();
+    const int n = n0 + (lc / CW) * TN * 32 + p * CW + lc % CW;   // this thread's channels
+    const bool nok = n < cout;
+    const int nc = nok ? n : 0;
+    float bv[VEC];
+    if constexpr (EPI == EPI_FWD) {
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const f32x4 b = *(const f32x4 *)(a.bias + nc + 4 * q);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) bv[4 * q + e] = b[e];
+      }
+    }
+    T *outb = a.out ? (T *)a.out + slot * a.out_ss + n : nullptr;
+    // the first group's loads are in flight while the accumulators go to LDS
+    if (fwd_rc || bwd_rc || bwd_mask) load_group(0, nc);
+    if (p > 0) lds_barrier();
 #pragma unroll
     for (int tm = 0; tm < TM; ++tm)
 #pragma unroll
@@ -341,101 +425,92 @@ __device__ __forceinline__ void conv_epilogue(f32x16 (&acc)[PH * 32 / (WM * 32)]
           const int m = wm * TM * 32 + tm * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
           so[m * RSW + wn * CW + tq * 32 + l32] = acc[tm][p * TNP + tq][r];
         }
-    __syncthreads();
-#pragma unroll 2
-    for (int i = 0; i < BM * CPR / NT; ++i) {
-      const int idx = tid + i * NT;
-      const int m = idx / CPR, lc = (idx % CPR) * VEC;
-      const int n = n0 + (lc / CW) * TN * 32 + p * CW + lc % CW;
-      const int py = y0 + m / PW, px = x0 + m % PW;
-      if (py >= h || px >= w || n >= cout) continue;
-      const long long pix = (long long)py * w + px;
-      float v[VEC];
-#pragma unroll
-      for (int q = 0; q < VEC / 4; ++q) {
-        const f32x4 u = *(const f32x4 *)(&so[m * RSW + lc + 4 * q]);
-        v[4 * q] = u[0]; v[4 * q + 1] = u[1]; v[4 * q + 2] = u[2]; v[4 * q + 3] = u[3];
-      }
-      if (EPI == EPI_FWD) {
-#pragma unroll
-        for (int q = 0; q < VEC / 4; ++q) {
-          const f32x4 b = *(const f32x4 *)(a.bias + n + 4 * q);
-#pragma unroll
-          for (int e = 0; e < 4; ++e) v[4 * q + e] = fmaxf(v[4 * q + e] + b[e], 0.f);
-        }
-        if (a.rc) {
-          const float *f = a.fc + ((long long)(g.gy[t] + py) * a.fc_w + (g.gx[t] + px)) * cout + n;
-          float *rc = a.rc + slot * a.rc_ss + pix * cout + n;
-#pragma unroll
-          for (int q = 0; q < VEC / 4; ++q) {
-            f32x4 d;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) d[e] = v[4 * q + e] - f[4 * q + e];
-            *(f32x4 *)(rc + 4 * q) = d;
-          }
-        }
-      } else {
-        if (a.rc) {
-          const float *rc = a.rc + slot * a.rc_ss + pix * cout + n;
-#pragma unroll
-          for (int q = 0; q < VEC / 4; ++q) {
-            const f32x4 d = *(const f32x4 *)(rc + 4 * q);
-#pragma unroll
-            for (int e = 0; e < 4; ++e) v[4 * q + e] += a.two_alpha * d[e];
-          }
-        }
-        if (a.mask) {
-          const TV mk = *(const TV *)((const T *)a.mask + slot * a.mask_ss + pix * cout + n);
-#pragma unroll
-          for (int e = 0; e < VEC; ++e)
-            if (!(to_f(mk[e]) > 0.f)) v[e] = 0.f;
-        }
-      }
-      if (EPI == EPI_FWD && !a.out) continue;
-      TV o;
-#pragma unroll
-      for (int e = 0; e < VEC; ++e) o[e] = from_f<T>(v[e]);
-      *(TV *)((T *)a.out + slot * a.out_ss + pix * cout + n) = o;
-    }
+    lds_barrier();
     if constexpr (EPI == EPI_FWD) {
-      // phase 3: 2 x 2 max pool of the pass's channels (patch origins are even, so every
-      // pooling window lies in one patch); the values compared are the rounded post-ReLU
-      // outputs, first maximum in row-major window order, as a separate pooling pass would
-      if (a.pool) {
-        constexpr int PWO = PW / 2, PO = (PH / 2) * PWO;
-        const int ho = h >> 1, wo = w >> 1;
-        for (int i = tid; i < PO * CPR; i += NT) {
-          const int q = i / CPR, lc = (i % CPR) * VEC;
-          const int n = n0 + (lc / CW) * TN * 32 + p * CW + lc % CW;
-          const int qy = q / PWO, qx = q % PWO;
-          const int oy = (y0 >> 1) + qy, ox = (x0 >> 1) + qx;
-          if (oy >= ho || ox >= wo || n >= cout) continue;
-          float bv[VEC];
+      T *poolb = a.pool ? (T *)a.pool + slot * a.pool_ss + n : nullptr;
+      const int ho = h >> 1, wo = w >> 1;
 #pragma unroll
-          for (int qq = 0; qq < VEC / 4; ++qq) {
-            const f32x4 b = *(const f32x4 *)(a.bias + n + 4 * qq);
-            bv[4 * qq] = b[0]; bv[4 * qq + 1] = b[1]; bv[4 * qq + 2] = b[2]; bv[4 * qq + 3] = b[3];
+      for (int k = 0; k < NW; ++k) {
+        if (k > 0 && k % GW == 0 && fwd_rc) load_group(4 * k, nc);
+        TV best;
+        float bf[VEC];
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          int ly, lx;
+          item_fwd(k, kk, ly, lx);
+          const int m = ly * PW + lx;
+          const int py = y0 + ly, px = x0 + lx;
+          float v[VEC];
+#pragma unroll
+          for (int q = 0; q < NQ; ++q) {
+            const f32x4 u = *(const f32x4 *)(&so[m * RSW + lc + 4 * q]);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) v[4 * q + e] = fmaxf(u[e] + bv[4 * q + e], 0.f);
           }
-          TV best;
-          float bf[VEC];
+          TV o;
 #pragma unroll
-          for (int kk = 0; kk < 4; ++kk) {
-            const int m = (2 * qy + (kk >> 1)) * PW + 2 * qx + (kk & 1);
-#pragma unroll
-            for (int qq = 0; qq < VEC / 4; ++qq) {
-              const f32x4 u = *(const f32x4 *)(&so[m * RSW + lc + 4 * qq]);
-#pragma unroll
-              for (int e = 0; e < 4; ++e) {
-                const T tv = from_f<T>(fmaxf(u[e] + bv[4 * qq + e], 0.f));
-                const float f = to_f(tv);
-                if (kk == 0 || f > bf[4 * qq + e]) {
-                  bf[4 * qq + e] = f;
-                  best[4 * qq + e] = tv;
-                }
-              }
+          for (int e = 0; e < VEC; ++e) {
+            o[e] = from_f<T>(v[e]);
+            const float f = to_f(o[e]);
+            if (kk == 0 || f > bf[e]) {
+              bf[e] = f;
+              best[e] = o[e];
             }
           }
-          *(TV *)((T *)a.pool + slot * a.pool_ss + ((long long)oy * wo + ox) * cout + n) = best;
+          if (py < h && px < w && nok) {
+            const long long po = (long long)(py * w + px) * cout;
+            if (fwd_rc) {
+              const int j = (k % GW) * 4 + kk;
+              float *rc = a.rc + slot * a.rc_ss + n + po;
+#pragma unroll
+              for (int q = 0; q < NQ; ++q) {
+                f32x4 d;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) d[e] = v[4 * q + e] - dq[j][q][e];
+                *(f32x4 *)(rc + 4 * q) = d;
+              }
+            }
+            if (outb) *(TV *)(outb + po) = o;
+          }
+        }
+        if (poolb) {
+          const int q = ib + k * QSTEP;
+          const int oy = (y0 >> 1) + q / PWO, ox = (x0 >> 1) + q % PWO;   // patch origins are even
+          if (oy < ho && ox < wo && nok) *(TV *)(poolb + (long long)(oy * wo + ox) * cout) = best;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int g0 = 0; g0 < NIT; g0 += G) {
+        if (g0 > 0 && (bwd_rc || bwd_mask)) load_group(g0, nc);
+#pragma unroll
+        for (int j = 0; j < G; ++j) {
+          int ly, lx;
+          item_bwd(g0 + j, ly, lx);
+          const int m = ly * PW + lx;
+          const int py = y0 + ly, px = x0 + lx;
+          if (py >= h || px >= w || !nok) continue;
+          float v[VEC];
+#pragma unroll
+          for (int q = 0; q < NQ; ++q) {
+            const f32x4 u = *(const f32x4 *)(&so[m * RSW + lc + 4 * q]);
+            v[4 * q] = u[0]; v[4 * q + 1] = u[1]; v[4 * q + 2] = u[2]; v[4 * q + 3] = u[3];
+          }
+          if (bwd_rc) {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q)
+#pragma unroll
+              for (int e = 0; e < 4; ++e) v[4 * q + e] += a.two_alpha * dq[j][q][e];
+          }
+          if (bwd_mask) {
+#pragma unroll
+            for (int e = 0; e < VEC; ++e)
+              if (!(to_f(mk[j][e]) > 0.f)) v[e] = 0.f;
+          }
+          TV o;
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) o[e] = from_f<T>(v[e]);
+          *(TV *)(outb + (long long)(py * w + px) * cout) = o;
         }
       }
     }
@@ -445,13 +520,6 @@ __device__ __forceinline__ void conv_epilogue(f32x16 (&acc)[PH * 32 / (WM * 32)]
 __device__ __attribute__((aligned(16))) unsigned kZeroRow[4] = {0u, 0u, 0u, 0u};
 
 typedef __attribute__((address_space(3))) void lds_void;
-
-// Workgroup barrier for the conv stage loops: waits for this wave's LDS reads and writes
-// (lgkmcnt 0), not for its global loads.  __syncthreads() (and an LDS-only fence, which
-// counts LDS DMA as pending LDS writes) would wait for every outstanding load, vmcnt 0;
-// here the stage code waits explicitly for the DMA that the next stage reads and leaves
-// later DMA (the next chunk's halo) in flight.  The asm is a compiler memory barrier.
-__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
 template <typename T, int NT, int ANVD, int AUNITS, int VEC>
 __device__ __forceinline__ void dma_a(T *__restrict__ dst, const T *base, const unsigned (&arel)[ANVD],
@@ -742,7 +810,7 @@ __device__ __forceinline__ void img_patch_load(float (&v)[4], const ConvArgs &a,
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_conv_img(ConvArgs a, Batch g) {
+__global__ __launch_bounds__(256, kImgBlocksPerCU) void k_conv_img(ConvArgs a, Batch g) {
   constexpr int PH = 8, PW = 32, BM = 256, BN = 64, TM = 2, TN = 2, KP = 32;
   constexpr int HP = PH + 2, WP = PW + 2;               // image patch with its 1-pixel halo
   constexpr int RS = KP + 16 / (int)sizeof(T);         // LDS row stride (elements), 16 B pad
