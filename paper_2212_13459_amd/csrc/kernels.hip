@@ -521,26 +521,40 @@ __device__ __attribute__((aligned(16))) unsigned kZeroRow[4] = {0u, 0u, 0u, 0u};
 
 typedef __attribute__((address_space(3))) void lds_void;
 
-template <typename T, int NT, int ANVD, int AUNITS, int VEC>
+// One 16-byte LDS DMA unit per lane: unit i of the wave writes LDS at dst + (i NT + 64 wv)
+// units + 16 bytes x lane.  A unit that is off (no next stage, halo position outside the
+// window or in the padding) reads the zero row, so every wave issues every unit and the
+// issue has no branches; an off unit only ever writes a buffer that is not read again
+// (the last stage's free buffers) or the padding of the halo buffer.
+template <typename T, int NT, int VEC>
+__device__ __forceinline__ void dma_unit_b(T *__restrict__ dst, const T *wbase, unsigned boff, bool on, int i,
+                                           int wv) {
+  const void *gp = on ? (const void *)((const char *)wbase + boff) : (const void *)kZeroRow;
+  __builtin_amdgcn_global_load_lds(gp, (lds_void *)(dst + (i * NT + wv * 64) * VEC), 16, 0, 0);
+}
+
+template <typename T, int NT, int VEC>
+__device__ __forceinline__ void dma_unit_a(T *__restrict__ dst, const T *base, unsigned arel, bool on, int cin,
+                                           int i, int wv, int tid) {
+  const unsigned unit = (unsigned)((i * NT + tid) % 5);
+  const unsigned off = (arel * (unsigned)cin + unit * VEC) * (unsigned)sizeof(T);
+  const void *gp = on ? (const void *)((const char *)base + off) : (const void *)kZeroRow;
+  __builtin_amdgcn_global_load_lds(gp, (lds_void *)(dst + (i * NT + wv * 64) * VEC), 16, 0, 0);
+}
+
+template <typename T, int NT, int ANVD, int VEC>
 __device__ __forceinline__ void dma_a(T *__restrict__ dst, const T *base, const unsigned (&arel)[ANVD],
                                       unsigned okbits, int cin, int wv, int tid) {
 #pragma unroll
-  for (int i = 0; i < ANVD; ++i) {
-    if (i * NT + wv * 64 >= AUNITS) break;   // the wave's 64 units lie past the patch
-    const unsigned unit = (unsigned)((i * NT + tid) % 5);
-    const unsigned off = (arel[i] * (unsigned)cin + unit * VEC) * (unsigned)sizeof(T);
-    const void *gp = ((okbits >> i) & 1u) ? (const void *)((const char *)base + off) : (const void *)kZeroRow;
-    __builtin_amdgcn_global_load_lds(gp, (lds_void *)(dst + (i * NT + wv * 64) * VEC), 16, 0, 0);
-  }
+  for (int i = 0; i < ANVD; ++i)
+    dma_unit_a<T, NT, VEC>(dst, base, arel[i], (okbits >> i) & 1u, cin, i, wv, tid);
 }
 
 template <typename T, int NT, int BNV, int VEC>
 __device__ __forceinline__ void dma_b(T *__restrict__ dst, const T *wbase, const unsigned (&boff)[BNV],
                                       int wv) {
 #pragma unroll
-  for (int i = 0; i < BNV; ++i)
-    __builtin_amdgcn_global_load_lds((const void *)((const char *)wbase + boff[i]),
-                                     (lds_void *)(dst + (i * NT + wv * 64) * VEC), 16, 0, 0);
+  for (int i = 0; i < BNV; ++i) dma_unit_b<T, NT, VEC>(dst, wbase, boff[i], true, i, wv);
 }
 
 // Weight-row offsets with the LDS swizzle on the global side: unit p = i NT + tid of a
@@ -559,11 +573,14 @@ __device__ __forceinline__ void dma_boff(unsigned (&boff)[BNV], int nrows, int c
   }
 }
 
-// One stage: issue DMA (weights for the next stage, then optionally a halo chunk), then
-// the k-step pipeline over this stage's buffers, then wait for this wave's DMA except the
-// last VMW loads (the caller's barrier follows).
-template <typename T, int TM, int TN, int BN, int CK, int VEC, int NTAP, int NT, int ANVD, int AUNITS, int BNV,
-          bool DA, int VMW>
+// One stage: the k-step pipeline over this stage's buffers, with the DMA of the next
+// stage's weights (then optionally the next halo chunk) spread over its first KD k-steps,
+// then a wait for this wave's DMA except the last VMW loads (the caller's barrier
+// follows).  Spreading the DMA keeps the CU's address and L1 path (about 64 bytes per
+// clock) below saturation; issued all at once after the barrier, the DMA of the four
+// waves would stall them for most of a thousand cycles before the first MFMA.
+template <typename T, int TM, int TN, int BN, int CK, int VEC, int NTAP, int NT, int ANVD, int BNV, bool DA,
+          int VMW>
 __device__ __forceinline__ void stage_dma(f32x16 (&acc)[TM][TN], const T *__restrict__ A,
                                           const T *__restrict__ B, const int (&pidx)[TM], int toff0, int bcol,
                                           int half, T *__restrict__ adst, const T *abase,
@@ -571,48 +588,65 @@ __device__ __forceinline__ void stage_dma(f32x16 (&acc)[TM][TN], const T *__rest
                                           T *__restrict__ bdst, const T *wbase, const unsigned (&boff)[BNV],
                                           bool issue_b, bool issue_a, int wv, int tid) {
   constexpr int NK = 2 * NTAP;
+  constexpr int ND = BNV + (DA ? ANVD : 0);   // DMA units per lane: weights first, then halo
+  constexpr int KD = NK < 4 ? NK : 4;         // k-steps that issue DMA
+  constexpr int DPK = (ND + KD - 1) / KD;
+  const bool aon = DA && issue_a;
   KFrag<TM, TN> f[2];
-  // the first k-step's fragment reads go out before the DMA instructions, whose issue then
-  // covers their latency (the DMA writes the other buffers); a single wait before the
-  // first MFMA follows
   load_kstep<T, TM, TN, BN, CK, VEC>(f[0], A, B, pidx, toff0, 0, 0, bcol, half);
-  __builtin_amdgcn_sched_barrier(0);
-  if (issue_b) dma_b<T, NT, BNV, VEC>(bdst, wbase, boff, wv);
-  if (DA && issue_a) dma_a<T, NT, ANVD, AUNITS, VEC>(adst, abase, arel, okbits, cin, wv, tid);
+  // all of the first k-step's reads (lgkmcnt 0): the compiler counts pending LDS DMA as
+  // LDS traffic and would otherwise wait again inside the k-step, after the next
+  // fragment reads have started
+  __builtin_amdgcn_s_waitcnt(0xc07f);
   __builtin_amdgcn_sched_barrier(0);
   // the next k-step's NLD fragment reads are interleaved with the first MFMAs of this
-  // k-step (R MFMAs, then one read), so they are in flight during the rest of it, the
+  // k-step (one MFMA, then one read), so they are in flight during the rest of it, the
   // LDS counter (4 bits) never tracks two k-steps of reads, and the only LDS wait of a
   // k-step, before its first MFMA, covers reads issued during the previous one.  With
-  // fewer than two MFMAs per read the reads all go first.
+  // fewer than two MFMAs per read the reads all go first.  The k-step's DMA units follow
+  // its MFMAs one by one.
   constexpr int NLD = TM + TN, NMF = TM * TN * (sizeof(T) == 2 ? 1 : 4);
-  constexpr int R = NMF / (2 * NLD) > 0 ? NMF / (2 * NLD) : 1;
-  constexpr int REST = NMF - NLD * R;
 #pragma unroll
   for (int j = 0; j < NK; ++j) {
     if (j + 1 < NK)
       load_kstep<T, TM, TN, BN, CK, VEC>(f[(j + 1) & 1], A, B, pidx, toff0 + (j + 1) / 2, (j + 1) / 2,
                                          (j + 1) & 1, bcol, half);
     mma_kstep<T, TM, TN>(acc, f[j & 1]);
-    if (j + 1 < NK) {
-      if constexpr (NMF >= 2 * NLD) {
+    const int u0 = j * DPK, u1 = (j + 1) * DPK < ND ? (j + 1) * DPK : ND;
 #pragma unroll
-        for (int q = 0; q < NLD; ++q) {
-          __builtin_amdgcn_sched_group_barrier(0x008, R, 0);   // R MFMAs
-          __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // one LDS read
-        }
-        if constexpr (REST > 0) __builtin_amdgcn_sched_group_barrier(0x008, REST, 0);
-      } else {
-        // few MFMAs per k-step (two waves per SIMD): all reads first
-        __builtin_amdgcn_sched_group_barrier(0x100, NLD, 0);
-        __builtin_amdgcn_sched_group_barrier(0x008, NMF, 0);
+    for (int u = u0; u < u1; ++u) {
+      if (u < BNV)
+        dma_unit_b<T, NT, VEC>(bdst, wbase, boff[u], issue_b, u, wv);
+      else
+        dma_unit_a<T, NT, VEC>(adst, abase, arel[u - BNV], aon && ((okbits >> (u - BNV)) & 1u), cin, u - BNV, wv,
+                               tid);
+    }
+    const int nld = j + 1 < NK ? NLD : 0, ndma = u1 > u0 ? u1 - u0 : 0;
+    if constexpr (NMF >= 2 * NLD) {
+#pragma unroll
+      for (int q = 0; q < NMF; ++q) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);                // one MFMA
+        if (q < nld) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // one LDS read
+        if (q < ndma) __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);  // one DMA unit
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < NLD; ++q)
+        if (q < nld) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+#pragma unroll
+      for (int q = 0; q < NMF; ++q) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        if (q < ndma) __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
       }
     }
+#pragma unroll
+    for (int q = NMF; q < DPK; ++q)
+      if (q < ndma) __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
     __builtin_amdgcn_sched_barrier(0);
   }
   // wait for this wave's loads; a halo chunk issued in this stage (the last VMW loads, as
   // loads complete in issue order) may stay in flight
-  if (DA && issue_a)
+  if (aon)
     __builtin_amdgcn_s_waitcnt(0xf70 | VMW);
   else
     __builtin_amdgcn_s_waitcnt(0xf70);
@@ -629,7 +663,7 @@ __global__ __launch_bounds__(WM * WN * 64) void k_conv3(ConvArgs a, Batch g) {
   constexpr int HP = PH + 2, WP = PW + 2;
   constexpr int AROWS = HP * WP;
   constexpr int ANVD = (AROWS * 5 + NT - 1) / NT;   // 16-byte units per thread per halo chunk
-  constexpr int AUNITS = (AROWS * 5 + 63) / 64 * 64;  // units written (whole waves)
+  constexpr int AUNITS = ANVD * NT;                   // units written (every wave, padding included)
   constexpr int BNV = (3 * BN * 4 + NT - 1) / NT;
   constexpr int ASZ = AUNITS * VEC, BSZ = BNV * NT * VEC;
   static_assert(ANVD <= 32, "halo mask bits");
@@ -703,14 +737,13 @@ __global__ __launch_bounds__(WM * WN * 64) void k_conv3(ConvArgs a, Batch g) {
   const long long wrow = (long long)a.cout_pad * CK;
 
   T *const A0 = sm, *const A1 = sm + ASZ, *const B0 = sm + 2 * ASZ, *const B1 = sm + 2 * ASZ + BSZ;
-  dma_a<T, NT, ANVD, AUNITS, VEC>(A0, abase0, arel, okbits, a.cin, wv, tid);
+  dma_a<T, NT, ANVD, VEC>(A0, abase0, arel, okbits, a.cin, wv, tid);
   dma_b<T, NT, BNV, VEC>(B0, wp0, boff, wv);
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   const int bcol = wn * TN * 32 + l32;
-  // halo loads the slowest wave issues per chunk (a stage may leave them in flight)
-  constexpr int AMIN = (AUNITS - (NT / 64 - 1) * 64 + NT - 1) / NT;
-  static_assert(AMIN >= 1 && AMIN <= 15, "vmcnt range");
+  // halo loads per chunk and wave (a stage may leave them in flight)
+  static_assert(ANVD >= 1 && ANVD <= 15, "vmcnt range");
 #pragma unroll 1
   for (int c = 0; c < nck; ++c) {
     const bool odd = c & 1;
@@ -721,19 +754,19 @@ __global__ __launch_bounds__(WM * WN * 64) void k_conv3(ConvArgs a, Batch g) {
     // filter row 0 (B buffer x): prefetch row 1 into y, then the next chunk's halo patch
     // (or segment 1's) into the other A buffer, which has two stages to arrive
     const T *anext = more ? abase0 + (c + 1) * CK : (SEG2 ? in1 + ((long long)by * w + bx) * a.cin2 : abase0);
-    stage_dma<T, TM, TN, BN, CK, VEC, 3, NT, ANVD, AUNITS, BNV, true, AMIN>(
+    stage_dma<T, TM, TN, BN, CK, VEC, 3, NT, ANVD, BNV, true, ANVD>(
         acc, Ac, Bx, pidx, 0, bcol, half, An, anext, arel, okbits, more ? a.cin : a.cin2, By,
         wp0 + (c * 9 + 3) * wrow, boff, true, more || seg, wv, tid);
     lds_barrier();
     // filter row 1 (y); prefetch row 2 into x (the halo patch lands with it)
-    stage_dma<T, TM, TN, BN, CK, VEC, 3, NT, ANVD, AUNITS, BNV, false, 0>(
+    stage_dma<T, TM, TN, BN, CK, VEC, 3, NT, ANVD, BNV, false, 0>(
         acc, Ac, By, pidx, WP, bcol, half, nullptr, nullptr, arel, okbits, 0, Bx, wp0 + (c * 9 + 6) * wrow, boff,
         true, false, wv, tid);
     lds_barrier();
     // filter row 2 (x); prefetch the next chunk's row 0 (or segment 1's weights) into y
     if (seg) dma_boff<T, NT, BNV, BN, CK, VEC>(boff, 1, a.cout_pad, n0, tid);
     const T *wnext = more ? wp0 + (c + 1) * 9 * wrow : wp1;
-    stage_dma<T, TM, TN, BN, CK, VEC, 3, NT, ANVD, AUNITS, BNV, false, 0>(
+    stage_dma<T, TM, TN, BN, CK, VEC, 3, NT, ANVD, BNV, false, 0>(
         acc, Ac, Bx, pidx, 2 * WP, bcol, half, nullptr, nullptr, arel, okbits, 0, By, wnext, boff, more || seg,
         false, wv, tid);
     lds_barrier();
@@ -744,7 +777,7 @@ __global__ __launch_bounds__(WM * WN * 64) void k_conv3(ConvArgs a, Batch g) {
     for (int c2 = 0; c2 < nck2; ++c2) {
       const int st = 3 * nck + c2, ac = nck + c2;
       const bool more = c2 + 1 < nck2;
-      stage_dma<T, TM, TN, BN, CK, VEC, 1, NT, ANVD, AUNITS, BNV, true, 0>(
+      stage_dma<T, TM, TN, BN, CK, VEC, 1, NT, ANVD, BNV, true, 0>(
           acc, (ac & 1) ? A1 : A0, (st & 1) ? B1 : B0, pidx, WP + 1, bcol, half, (ac & 1) ? A0 : A1,
           abase1 + (c2 + 1) * CK, arel, okbits, a.cin2, (st & 1) ? B0 : B1, wp1 + (long long)(c2 + 1) * wrow,
           boff, more, more, wv, tid);
