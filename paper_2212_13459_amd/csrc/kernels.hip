@@ -281,6 +281,10 @@ __device__ __forceinline__ void load_kstep(KFrag<TM, TN> &f, const T *A, const T
     f.b[tn] = *(const u32x4 *)(&B[swz64(ti * BN + bcol + tn * 32, chunk, CK, VEC)]);
 }
 
+// The weights fragment is the MFMA's first operand: block (tm, tn) accumulates the
+// transposed 32 x 32 tile, channels by pixels, so that lane (l32, half) holds pixel l32 of
+// the block and channels 8 (r / 4) + 4 half + (r mod 4) in element r: four consecutive
+// channels per group of four elements.
 template <typename T, int TM, int TN>
 __device__ __forceinline__ void mma_kstep(f32x16 (&acc)[TM][TN], const KFrag<TM, TN> &f) {
 #pragma unroll
@@ -288,23 +292,24 @@ __device__ __forceinline__ void mma_kstep(f32x16 (&acc)[TM][TN], const KFrag<TM,
 #pragma unroll
     for (int tn = 0; tn < TN; ++tn) {
       if constexpr (sizeof(T) == 2) {
-        acc[tm][tn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, f.a[tm]),
-                                                               __builtin_bit_cast(bf16x8, f.b[tn]),
+        acc[tm][tn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, f.b[tn]),
+                                                               __builtin_bit_cast(bf16x8, f.a[tm]),
                                                                acc[tm][tn], 0, 0, 0);
       } else {
         const f32x4 av = __builtin_bit_cast(f32x4, f.a[tm]), bv = __builtin_bit_cast(f32x4, f.b[tn]);
 #pragma unroll
         for (int j = 0; j < 4; ++j)
-          acc[tm][tn] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[j], bv[j], acc[tm][tn], 0, 0, 0);
+          acc[tm][tn] = __builtin_amdgcn_mfma_f32_32x32x2f32(bv[j], av[j], acc[tm][tn], 0, 0, 0);
       }
     }
 }
 
 // Passes of the LDS epilogue: the fewest that divide TN and fit the FP32 tile
-// (BM x (WN x TN / passes x 32 + 8) floats) into the stage buffers.
+// (BM x (WN x TN / passes x 32 + 4) floats) into the stage buffers.  A row pitch of 4
+// mod 64 words keeps the 16-byte writes of 16 consecutive pixels on distinct banks.
 constexpr int epi_passes(int bm, int wn, int tn, int smem_bytes) {
   for (int p = 1; p <= tn; ++p)
-    if (tn % p == 0 && bm * (wn * (tn / p) * 32 + 8) * 4 <= smem_bytes) return p;
+    if (tn % p == 0 && bm * (wn * (tn / p) * 32 + 4) * 4 <= smem_bytes) return p;
   return 0;
 }
 
@@ -339,7 +344,7 @@ __device__ __forceinline__ void conv_epilogue(f32x16 (&acc)[PH * 32 / (WM * 32)]
   constexpr int TM = BM / (WM * 32), TN = BN / (WN * 32);
   constexpr int VEC = 16 / sizeof(T), NQ = VEC / 4;
   constexpr int NPASS = epi_passes(BM, WN, TN, SMEM_BYTES);
-  constexpr int TNP = TN / NPASS, CW = TNP * 32, RSW = WN * CW + 8;
+  constexpr int TNP = TN / NPASS, CW = TNP * 32, RSW = WN * CW + 4;
   constexpr int CPR = WN * CW / VEC;
   static_assert(NT % CPR == 0 && PH % 2 == 0, "epilogue tiling");
   typedef T TV __attribute__((ext_vector_type(VEC)));
@@ -416,14 +421,17 @@ __device__ __forceinline__ void conv_epilogue(f32x16 (&acc)[PH * 32 / (WM * 32)]
     // the first group's loads are in flight while the accumulators go to LDS
     if (fwd_rc || bwd_rc || bwd_mask) load_group(0, nc);
     if (p > 0) lds_barrier();
+    // accumulator block (tm, tq): pixel l32, channels 8 jj + 4 half + (0..3) (see mma_kstep)
 #pragma unroll
     for (int tm = 0; tm < TM; ++tm)
 #pragma unroll
       for (int tq = 0; tq < TNP; ++tq)
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int m = wm * TM * 32 + tm * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
-          so[m * RSW + wn * CW + tq * 32 + l32] = acc[tm][p * TNP + tq][r];
+        for (int jj = 0; jj < 4; ++jj) {
+          const int m = wm * TM * 32 + tm * 32 + l32;
+          const f32x16 &av = acc[tm][p * TNP + tq];
+          const f32x4 v = {av[4 * jj], av[4 * jj + 1], av[4 * jj + 2], av[4 * jj + 3]};
+          *(f32x4 *)(&so[m * RSW + wn * CW + tq * 32 + 8 * jj + 4 * half]) = v;
         }
     lds_barrier();
     if constexpr (EPI == EPI_FWD) {
@@ -785,16 +793,18 @@ __global__ __launch_bounds__(WM * WN * 64) void k_conv3(ConvArgs a, Batch g) {
     }
   }
   if constexpr (EPI == EPI_STITCH) {
-    // image gradient (FP32 CHW) at the owned pixels: output columns 0..2 of the padded 32
+    // image gradient (FP32 CHW) at the owned pixels: channels 0..2 of the padded 32
+    // accumulator element r of lanes 0..31 is channel r of pixel l32 (see mma_kstep)
 #pragma unroll
-    for (int tm = 0; tm < TM; ++tm)
+    for (int tm = 0; tm < TM; ++tm) {
+      const int m = wm * TM * 32 + tm * 32 + l32;
+      const int py = y0 + m / PW, px = x0 + m % PW;
+      if (half == 0 && py < ey && px < ex) {
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int m = wm * TM * 32 + tm * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
-        const int py = y0 + m / PW, px = x0 + m % PW;
-        if (l32 < 3 && py < ey && px < ex)
-          a.grad[((long long)l32 * a.img_h + (g.gy[t] + py)) * a.img_w + (g.gx[t] + px)] = acc[tm][0][r];
+        for (int r = 0; r < 3; ++r)
+          a.grad[((long long)r * a.img_h + (g.gy[t] + py)) * a.img_w + (g.gx[t] + px)] = acc[tm][0][r];
       }
+    }
   } else {
     conv_epilogue<T, BN, WM, WN, PH, EPI, 2 * (ASZ + BSZ) * (int)sizeof(T)>(acc, sm, a, g, t, slot, y0, x0, h,
                                                                           w, n0, tid, wm, wn, l32, half);
@@ -925,7 +935,7 @@ __global__ __launch_bounds__(256, kImgBlocksPerCU) void k_conv_img(ConvArgs a, B
 #pragma unroll
       for (int tm = 0; tm < TM; ++tm)
 #pragma unroll
-        for (int tn = 0; tn < TN; ++tn) Mma<T>::mma(acc[tm][tn], af[tm], bfr[tn]);
+        for (int tn = 0; tn < TN; ++tn) Mma<T>::mma(acc[tm][tn], bfr[tn], af[tm]);   // channels x pixels
     } else {
 #pragma unroll
       for (int hh = 0; hh < 2; ++hh) {
@@ -944,7 +954,7 @@ __global__ __launch_bounds__(256, kImgBlocksPerCU) void k_conv_img(ConvArgs a, B
 #pragma unroll
         for (int tm = 0; tm < TM; ++tm)
 #pragma unroll
-          for (int tn = 0; tn < TN; ++tn) Mma<T>::mma(acc[tm][tn], af[tm], bfr[tn]);
+          for (int tn = 0; tn < TN; ++tn) Mma<T>::mma(acc[tm][tn], bfr[tn], af[tm]);
       }
     }
     __syncthreads();   // the epilogue reuses the im2col buffer
