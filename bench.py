@@ -160,7 +160,7 @@ def main():
     ap.add_argument("--m", type=int, default=155)
     ap.add_argument("--tile-batch", type=int, default=32)
     ap.add_argument("--ws-gib", type=float, default=200.0)
-    ap.add_argument("--cpu-sample", type=int, default=1024)
+    ap.add_argument("--cpu-sample", type=int, default=1440)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--recompute", action="store_true",
                     help="size the workspace for a tile batch, so that Step 2 recomputes each tile's "
