@@ -321,6 +321,126 @@ constexpr int epi_passes(int bm, int wn, int tn, int smem_bytes) {
 // stores between passes.  The asm is a compiler memory barrier.
 __device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
+// Single-pass BF16 epilogue (BF16 layers without the FP32 content residual): phase 1
+// applies bias + ReLU (forward) to the accumulators in registers, rounds to BF16 and
+// writes 8-byte rows of four channels to LDS (the whole BM x BN tile fits); phase 2 copies
+// 16-byte rows of eight channels to the output and, forward, takes the 2 x 2 pooling
+// maximum, backward, applies the ReLU mask.  Forward outputs have their sign bit cleared
+// (a ReLU output of -0 becomes +0), so all values are non-negative and the integer order of
+// their bits is their order as numbers: the integer maximum is the first maximum in
+// window order that a separate pooling pass would keep.  The mask is a selection, so
+// rounding before it gives the same bits as rounding after it.
+template <int BN, int WM, int WN, int PH, int EPI, int SMEM_BYTES>
+__device__ __forceinline__ void epi_bf16(f32x16 (&acc)[PH * 32 / (WM * 32)][BN / (WN * 32)], bf16 *sm,
+                                         const ConvArgs &a, long long slot, int y0, int x0, int h, int w, int n0,
+                                         int tid, int wm, int wn, int l32, int half) {
+  constexpr int PW = 32, BM = PH * PW, NT = WM * WN * 64;
+  constexpr int TM = BM / (WM * 32), TN = BN / (WN * 32);
+  constexpr int RS = BN + 8;   // row pitch in BF16: 4 mod 64 words for even BN / 32
+  static_assert(BM * RS * 2 <= SMEM_BYTES, "BF16 epilogue tile");
+  typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
+  typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+  const int cout = a.cout;
+  // phase 1: block (tm, tn), lane: pixel l32, channels 8 jj + 4 half + (0..3) (mma_kstep)
+#pragma unroll
+  for (int tn = 0; tn < TN; ++tn)
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) {
+      const int cl = wn * TN * 32 + tn * 32 + 8 * jj + 4 * half;
+      f32x4 b = {0.f, 0.f, 0.f, 0.f};
+      if constexpr (EPI == EPI_FWD) b = *(const f32x4 *)(a.bias + (n0 + cl < cout ? n0 + cl : 0));
+#pragma unroll
+      for (int tm = 0; tm < TM; ++tm) {
+        const int m = wm * TM * 32 + tm * 32 + l32;
+        u16x4 o;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          float v = acc[tm][tn][4 * jj + e];
+          if constexpr (EPI == EPI_FWD) v = fmaxf(v + b[e], 0.f);
+          o[e] = __builtin_bit_cast(unsigned short, (bf16)v);
+          if constexpr (EPI == EPI_FWD) o[e] &= (unsigned short)0x7fff;
+        }
+        *(u16x4 *)(&sm[m * RS + cl]) = o;
+      }
+      // one (tn, jj) group at a time: hoisting every accumulator read would need 256 VGPRs
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  lds_barrier();
+  // phase 2: thread chunk of eight channels lc (the same for all its items)
+  constexpr int CPR = BN / 8, ISTEP = NT / CPR;
+  static_assert(NT % CPR == 0, "epilogue items");
+  const int lc = (tid % CPR) * 8, ib = tid / CPR;
+  const int n = n0 + lc;
+  const bool nok = n < cout;
+  if constexpr (EPI == EPI_FWD) {
+    // 2 x 2 windows q = ib + k ISTEP (k < NW)
+    constexpr int PWO = PW / 2, PO = (PH / 2) * PWO, NW = PO * CPR / NT;
+    static_assert((PO * CPR) % NT == 0, "epilogue windows");
+    bf16 *outb = a.out ? (bf16 *)a.out + slot * a.out_ss + n : nullptr;
+    bf16 *poolb = a.pool ? (bf16 *)a.pool + slot * a.pool_ss + n : nullptr;
+    const int ho = h >> 1, wo = w >> 1;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+      const int q = ib + k * ISTEP;
+      const int qy = q / PWO, qx = q % PWO;
+      u16x8 best;
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const int ly = 2 * qy + (kk >> 1), lx = 2 * qx + (kk & 1);
+        const int py = y0 + ly, px = x0 + lx;
+        const u16x8 u = *(const u16x8 *)(&sm[(ly * PW + lx) * RS + lc]);
+        best = kk == 0 ? u : __builtin_elementwise_max(best, u);
+        if (outb && nok && py < h && px < w) *(u16x8 *)(outb + (long long)(py * w + px) * cout) = u;
+      }
+      const int oy = (y0 >> 1) + qy, ox = (x0 >> 1) + qx;   // patch origins are even
+      if (poolb && nok && oy < ho && ox < wo) *(u16x8 *)(poolb + (long long)(oy * wo + ox) * cout) = best;
+    }
+  } else {
+    // pixels m = ib + i ISTEP (i < NIT), masks loaded in groups of G
+    constexpr int NIT = BM * CPR / NT, G = NIT < 8 ? NIT : 8;
+    static_assert((BM * CPR) % NT == 0 && NIT % G == 0, "epilogue items");
+    static_assert(ISTEP % PW == 0 || PW % ISTEP == 0, "epilogue pixel stride");
+    auto item = [&](int i, int &ly, int &lx) __attribute__((always_inline)) {
+      if constexpr (ISTEP % PW == 0) {
+        ly = ib / PW + i * (ISTEP / PW);
+        lx = ib % PW;
+      } else {
+        ly = i / (PW / ISTEP);
+        lx = ib + (i % (PW / ISTEP)) * ISTEP;   // ib < ISTEP
+      }
+    };
+    bf16 *outb = (bf16 *)a.out + slot * a.out_ss + n;
+    const bf16 *mskb = a.mask ? (const bf16 *)a.mask + slot * a.mask_ss + (nok ? n : 0) : nullptr;
+#pragma unroll
+    for (int g0 = 0; g0 < NIT; g0 += G) {
+      u16x8 mk[G];
+      if (mskb) {
+#pragma unroll
+        for (int j = 0; j < G; ++j) {
+          int ly, lx;
+          item(g0 + j, ly, lx);
+          const int py = min(y0 + ly, h - 1), px = min(x0 + lx, w - 1);
+          mk[j] = *(const u16x8 *)(mskb + (long long)(py * w + px) * cout);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < G; ++j) {
+        int ly, lx;
+        item(g0 + j, ly, lx);
+        const int py = y0 + ly, px = x0 + lx;
+        if (py >= h || px >= w || !nok) continue;
+        u16x8 u = *(const u16x8 *)(&sm[(ly * PW + lx) * RS + lc]);
+        if (mskb) {
+#pragma unroll
+          for (int e = 0; e < 8; ++e)
+            if (!(__builtin_bit_cast(float, (unsigned)mk[j][e] << 16) > 0.f)) u[e] = 0;
+        }
+        *(u16x8 *)(outb + (long long)(py * w + px) * cout) = u;
+      }
+    }
+  }
+}
+
 // Conv epilogue through LDS (the caller's last barrier has released its stage buffers,
 // SMEM_BYTES of them at sm), in NPASS passes over the wave's TN column blocks: phase 1
 // writes the raw FP32 accumulators of the pass, phase 2 reads VEC consecutive channels of
@@ -335,7 +455,7 @@ __device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(
 // (residual, mask) are issued together, the first group before phase 1.  Addresses are a
 // per-pass base plus a 64-bit element offset (pixel index times cout: a whole-image
 // window can hold more than 2^31 elements).
-template <typename T, int BN, int WM, int WN, int PH, int EPI, int SMEM_BYTES>
+template <typename T, int BN, int WM, int WN, int PH, int EPI, int SMEM_BYTES, bool F32E>
 __device__ __forceinline__ void conv_epilogue(f32x16 (&acc)[PH * 32 / (WM * 32)][BN / (WN * 32)], T *sm,
                                               const ConvArgs &a, const Batch &g, int t, long long slot,
                                               int y0, int x0, int h, int w, int n0, int tid, int wm, int wn,
@@ -348,6 +468,13 @@ __device__ __forceinline__ void conv_epilogue(f32x16 (&acc)[PH * 32 / (WM * 32)]
   constexpr int CPR = WN * CW / VEC;
   static_assert(NT % CPR == 0 && PH % 2 == 0, "epilogue tiling");
   typedef T TV __attribute__((ext_vector_type(VEC)));
+  // BF16 without the content residual: single pass (the choice is a template argument,
+  // F32E, so that each kernel holds one epilogue: with both behind a run-time test the
+  // compiler copies every accumulator to VGPRs ahead of it and spills)
+  if constexpr (sizeof(T) == 2 && !F32E) {
+    epi_bf16<BN, WM, WN, PH, EPI, SMEM_BYTES>(acc, (bf16 *)sm, a, slot, y0, x0, h, w, n0, tid, wm, wn, l32, half);
+    return;
+  }
   float *so = (float *)sm;
   const int cout = a.cout;
   const int lc = (tid % CPR) * VEC, ib = tid / CPR;
@@ -660,7 +787,7 @@ __device__ __forceinline__ void stage_dma(f32x16 (&acc)[TM][TN], const T *__rest
     __builtin_amdgcn_s_waitcnt(0xf70);
 }
 
-template <typename T, int BN, int WM, int WN, int PH, int EPI, bool SEG2>
+template <typename T, int BN, int WM, int WN, int PH, int EPI, bool SEG2, bool F32E>
 __global__ __launch_bounds__(WM * WN * 64) void k_conv3(ConvArgs a, Batch g) {
   constexpr int PW = 32, BM = PH * PW;
   constexpr int NT = WM * WN * 64;
@@ -806,18 +933,18 @@ __global__ __launch_bounds__(WM * WN * 64) void k_conv3(ConvArgs a, Batch g) {
       }
     }
   } else {
-    conv_epilogue<T, BN, WM, WN, PH, EPI, 2 * (ASZ + BSZ) * (int)sizeof(T)>(acc, sm, a, g, t, slot, y0, x0, h,
-                                                                          w, n0, tid, wm, wn, l32, half);
+    conv_epilogue<T, BN, WM, WN, PH, EPI, 2 * (ASZ + BSZ) * (int)sizeof(T), F32E>(acc, sm, a, g, t, slot, y0, x0,
+                                                                                h, w, n0, tid, wm, wn, l32, half);
   }
 }
 
-template <typename T, int BN, int WM, int WN, int PH, int EPI, bool SEG2>
+template <typename T, int BN, int WM, int WN, int PH, int EPI, bool SEG2, bool F32E = false>
 static hipError_t run_conv3(const ConvArgs &a, const Batch &g, hipStream_t s) {
   const int nblk = g.pfx[g.n];
   if (nblk == 0) return hipSuccess;
   // one-dimensional grid in XCD-aware order (see k_conv3)
   dim3 grid(8 * ((nblk + 7) / 8) * ((a.cout + BN - 1) / BN));
-  hipLaunchKernelGGL((k_conv3<T, BN, WM, WN, PH, EPI, SEG2>), grid, dim3(WM * WN * 64), 0, s, a, g);
+  hipLaunchKernelGGL((k_conv3<T, BN, WM, WN, PH, EPI, SEG2, F32E>), grid, dim3(WM * WN * 64), 0, s, a, g);
   return hipGetLastError();
 }
 
@@ -958,8 +1085,8 @@ __global__ __launch_bounds__(256, kImgBlocksPerCU) void k_conv_img(ConvArgs a, B
       }
     }
     __syncthreads();   // the epilogue reuses the im2col buffer
-    conv_epilogue<T, BN, 4, 1, PH, EPI_FWD, SMEM>(acc, (T *)smem, a, g, t, slot, y0, x0, h, w, 0, tid, wave, 0,
-                                                  l32, half);
+    conv_epilogue<T, BN, 4, 1, PH, EPI_FWD, SMEM, false>(acc, (T *)smem, a, g, t, slot, y0, x0, h, w, 0, tid, wave,
+                                                         0, l32, half);
   }
 }
 
@@ -1030,9 +1157,14 @@ static hipError_t conv_dispatch(int in_mode, int epi, const ConvArgs &a, const B
     }
     if (in_mode != IN_NHWC) return hipErrorInvalidValue;
     if constexpr (sizeof(T) == 2) {
-      if (small) return run_conv3<T, 64, 4, 1, 8, EPI_FWD, false>(a, g, s);
-      if (a.cout % 256 == 0) return run_conv3<T, 256, 2, 2, 8, EPI_FWD, false>(a, g, s);
-      return run_conv3<T, 128, 4, 2, 8, EPI_FWD, false>(a, g, s);
+      // F32E: the content layer's FP32 residual needs the FP32 epilogue
+#define NST_CONV3_FWD(BN_, WM_, WN_, PH_)                                                  \
+  return a.rc ? run_conv3<T, BN_, WM_, WN_, PH_, EPI_FWD, false, true>(a, g, s)          \
+              : run_conv3<T, BN_, WM_, WN_, PH_, EPI_FWD, false, false>(a, g, s)
+      if (small) NST_CONV3_FWD(64, 4, 1, 8);
+      if (a.cout % 256 == 0) NST_CONV3_FWD(256, 2, 2, 8);
+      NST_CONV3_FWD(128, 4, 2, 8);
+#undef NST_CONV3_FWD
     } else {
       if (small) return run_conv3<T, 64, 4, 1, 8, EPI_FWD, false>(a, g, s);
       if (a.cout % 256 == 0) return run_conv3<T, 256, 2, 4, 8, EPI_FWD, false>(a, g, s);
@@ -1044,7 +1176,15 @@ static hipError_t conv_dispatch(int in_mode, int epi, const ConvArgs &a, const B
 #define NST_CONV3_BWD(BN_, WM_, WN_, PH_)                                                  \
   return seg2 ? run_conv3<T, BN_, WM_, WN_, PH_, EPI_BWD, true>(a, g, s)                  \
               : run_conv3<T, BN_, WM_, WN_, PH_, EPI_BWD, false>(a, g, s)
+#define NST_CONV3_BWD_RC(BN_, WM_, WN_, PH_)                                               \
+  return seg2 ? run_conv3<T, BN_, WM_, WN_, PH_, EPI_BWD, true, true>(a, g, s)            \
+              : run_conv3<T, BN_, WM_, WN_, PH_, EPI_BWD, false, true>(a, g, s)
     if constexpr (sizeof(T) == 2) {
+      if (a.rc) {   // the content residual enters in FP32 (F32E)
+        if (small) NST_CONV3_BWD_RC(64, 4, 1, 8);
+        if (a.cout % 256 == 0) NST_CONV3_BWD_RC(256, 2, 2, 8);
+        NST_CONV3_BWD_RC(128, 4, 2, 8);
+      }
       if (small) NST_CONV3_BWD(64, 4, 1, 8);
       if (a.cout % 256 == 0) NST_CONV3_BWD(256, 2, 2, 8);
       NST_CONV3_BWD(128, 4, 2, 8);
@@ -1054,6 +1194,7 @@ static hipError_t conv_dispatch(int in_mode, int epi, const ConvArgs &a, const B
       NST_CONV3_BWD(128, 4, 2, 8);
     }
 #undef NST_CONV3_BWD
+#undef NST_CONV3_BWD_RC
   }
   if (in_mode == IN_NONE) {
     if (small)
@@ -1077,12 +1218,14 @@ const char *conv_kernel_name(int precision, int in_mode, int epi, const ConvArgs
   }
   if (in_mode == IN_NHWC && epi != EPI_STITCH) {
     const Conv2Cfg k = conv2_cfg(precision, a.cout);
-    snprintf(o, 160, "void nst::k_conv3<%s, %d, %d, %d, %d, %d, %s>(nst::ConvArgs, nst::Batch)",
-             precision == 1 ? "__bf16" : "float", k.bn, k.wm, k.wn, k.ph, epi, seg2 ? "true" : "false");
+    const bool f32e = precision == 1 && a.rc != nullptr;
+    snprintf(o, 160, "void nst::k_conv3<%s, %d, %d, %d, %d, %d, %s, %s>(nst::ConvArgs, nst::Batch)",
+             precision == 1 ? "__bf16" : "float", k.bn, k.wm, k.wn, k.ph, epi, seg2 ? "true" : "false",
+             f32e ? "true" : "false");
     return o;
   }
   if (epi == EPI_STITCH) {
-    snprintf(o, 160, "void nst::k_conv3<%s, 32, 4, 1, 8, %d, false>(nst::ConvArgs, nst::Batch)",
+    snprintf(o, 160, "void nst::k_conv3<%s, 32, 4, 1, 8, %d, false, false>(nst::ConvArgs, nst::Batch)",
              precision == 1 ? "__bf16" : "float", EPI_STITCH);
     return o;
   } else if (a.cout <= 64) {
