@@ -709,26 +709,31 @@ __device__ __forceinline__ void dma_boff(unsigned (&boff)[BNV], int nrows, int c
 }
 
 // One stage: the k-step pipeline over this stage's buffers, with the DMA of the next
-// stage's weights (then optionally the next halo chunk) spread over its first KD k-steps,
-// then a wait for this wave's DMA except the last VMW loads (the caller's barrier
-// follows).  Spreading the DMA keeps the CU's address and L1 path (about 64 bytes per
-// clock) below saturation; issued all at once after the barrier, the DMA of the four
-// waves would stall them for most of a thousand cycles before the first MFMA.
+// stage's weights (then optionally the next halo chunk) spread over its first KD k-steps
+// (at most four, never the last).  Spreading the DMA keeps the CU's address and L1 path
+// (about 64 bytes per clock) below saturation; issued all at once after a barrier, the
+// DMA of the four waves would stall them for most of a thousand cycles before the first
+// MFMA.
+//   f[0] holds the stage's first k-step fragments on entry.  The last k-step's fragments
+// are in registers before it starts, so halfway through its MFMAs the stage is done with
+// its buffers: it waits for this wave's DMA except the last VMW loads (a halo chunk left
+// in flight), passes the workgroup barrier, reads the next stage's first fragments
+// (buffers An, Bn, offset toffn) into f[0], and then runs the second half of the MFMAs,
+// which cover the latency of those reads.
 template <typename T, int TM, int TN, int BN, int CK, int VEC, int NTAP, int NT, int ANVD, int BNV, bool DA,
           int VMW>
-__device__ __forceinline__ void stage_dma(f32x16 (&acc)[TM][TN], const T *__restrict__ A,
+__device__ __forceinline__ void stage_dma(f32x16 (&acc)[TM][TN], KFrag<TM, TN> (&f)[2], const T *__restrict__ A,
                                           const T *__restrict__ B, const int (&pidx)[TM], int toff0, int bcol,
                                           int half, T *__restrict__ adst, const T *abase,
                                           const unsigned (&arel)[ANVD], unsigned okbits, int cin,
                                           T *__restrict__ bdst, const T *wbase, const unsigned (&boff)[BNV],
-                                          bool issue_b, bool issue_a, int wv, int tid) {
+                                          bool issue_b, bool issue_a, const T *__restrict__ An,
+                                          const T *__restrict__ Bn, int toffn, bool has_next, int wv, int tid) {
   constexpr int NK = 2 * NTAP;
   constexpr int ND = BNV + (DA ? ANVD : 0);   // DMA units per lane: weights first, then halo
-  constexpr int KD = NK < 4 ? NK : 4;         // k-steps that issue DMA
+  constexpr int KD = NK - 1 < 4 ? NK - 1 : 4;  // k-steps that issue DMA (never the last)
   constexpr int DPK = (ND + KD - 1) / KD;
   const bool aon = DA && issue_a;
-  KFrag<TM, TN> f[2];
-  load_kstep<T, TM, TN, BN, CK, VEC>(f[0], A, B, pidx, toff0, 0, 0, bcol, half);
   // all of the first k-step's reads (lgkmcnt 0): the compiler counts pending LDS DMA as
   // LDS traffic and would otherwise wait again inside the k-step, after the next
   // fragment reads have started
@@ -746,6 +751,56 @@ __device__ __forceinline__ void stage_dma(f32x16 (&acc)[TM][TN], const T *__rest
     if (j + 1 < NK)
       load_kstep<T, TM, TN, BN, CK, VEC>(f[(j + 1) & 1], A, B, pidx, toff0 + (j + 1) / 2, (j + 1) / 2,
                                          (j + 1) & 1, bcol, half);
+    if (j == NK - 1) {
+      // last k-step: the first half of its MFMAs (same operand order as mma_kstep), the
+      // stage's waits and barrier, the next stage's first reads, the second half
+      const KFrag<TM, TN> &fl = f[j & 1];
+#pragma unroll
+      for (int tm = 0; tm < TM / 2; ++tm)
+#pragma unroll
+        for (int tn = 0; tn < TN; ++tn) {
+          if constexpr (sizeof(T) == 2) {
+            acc[tm][tn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, fl.b[tn]),
+                                                                   __builtin_bit_cast(bf16x8, fl.a[tm]),
+                                                                   acc[tm][tn], 0, 0, 0);
+          } else {
+            const f32x4 av = __builtin_bit_cast(f32x4, fl.a[tm]), bv = __builtin_bit_cast(f32x4, fl.b[tn]);
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+              acc[tm][tn] = __builtin_amdgcn_mfma_f32_32x32x2f32(bv[q], av[q], acc[tm][tn], 0, 0, 0);
+          }
+        }
+      __builtin_amdgcn_sched_barrier(0);
+      // a halo chunk issued in this stage (the last VMW loads, as loads complete in issue
+      // order) may stay in flight; lgkmcnt 0 visible to the compiler, so that it does not
+      // wait for the next stage's reads before the second half
+      if (aon)
+        __builtin_amdgcn_s_waitcnt(0xf70 | VMW);
+      else
+        __builtin_amdgcn_s_waitcnt(0xf70);
+      __builtin_amdgcn_s_waitcnt(0xc07f);
+      lds_barrier();
+      KFrag<TM, TN> keep = fl;   // f[0] is overwritten by the next stage's reads
+      if (has_next) load_kstep<T, TM, TN, BN, CK, VEC>(f[0], An, Bn, pidx, toffn, 0, 0, bcol, half);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int tm = TM / 2; tm < TM; ++tm)
+#pragma unroll
+        for (int tn = 0; tn < TN; ++tn) {
+          if constexpr (sizeof(T) == 2) {
+            acc[tm][tn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, keep.b[tn]),
+                                                                   __builtin_bit_cast(bf16x8, keep.a[tm]),
+                                                                   acc[tm][tn], 0, 0, 0);
+          } else {
+            const f32x4 av = __builtin_bit_cast(f32x4, keep.a[tm]), bv = __builtin_bit_cast(f32x4, keep.b[tn]);
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+              acc[tm][tn] = __builtin_amdgcn_mfma_f32_32x32x2f32(bv[q], av[q], acc[tm][tn], 0, 0, 0);
+          }
+        }
+      __builtin_amdgcn_sched_barrier(0);
+      continue;
+    }
     mma_kstep<T, TM, TN>(acc, f[j & 1]);
     const int u0 = j * DPK, u1 = (j + 1) * DPK < ND ? (j + 1) * DPK : ND;
 #pragma unroll
@@ -760,9 +815,9 @@ __device__ __forceinline__ void stage_dma(f32x16 (&acc)[TM][TN], const T *__rest
     if constexpr (NMF >= 2 * NLD) {
 #pragma unroll
       for (int q = 0; q < NMF; ++q) {
-        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);                // one MFMA
-        if (q < nld) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // one LDS read
-        if (q < ndma) __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);  // one DMA unit
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        if (q < nld) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+        if (q < ndma) __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
       }
     } else {
 #pragma unroll
@@ -779,12 +834,6 @@ __device__ __forceinline__ void stage_dma(f32x16 (&acc)[TM][TN], const T *__rest
       if (q < ndma) __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
     __builtin_amdgcn_sched_barrier(0);
   }
-  // wait for this wave's loads; a halo chunk issued in this stage (the last VMW loads, as
-  // loads complete in issue order) may stay in flight
-  if (aon)
-    __builtin_amdgcn_s_waitcnt(0xf70 | VMW);
-  else
-    __builtin_amdgcn_s_waitcnt(0xf70);
 }
 
 template <typename T, int BN, int WM, int WN, int PH, int EPI, bool SEG2, bool F32E>
@@ -879,6 +928,10 @@ __global__ __launch_bounds__(WM * WN * 64) void k_conv3(ConvArgs a, Batch g) {
   const int bcol = wn * TN * 32 + l32;
   // halo loads per chunk and wave (a stage may leave them in flight)
   static_assert(ANVD >= 1 && ANVD <= 15, "vmcnt range");
+  // each stage passes the workgroup barrier itself and leaves the next stage's first
+  // fragments in fr[0]
+  KFrag<TM, TN> fr[2];
+  load_kstep<T, TM, TN, BN, CK, VEC>(fr[0], A0, B0, pidx, 0, 0, 0, bcol, half);
 #pragma unroll 1
   for (int c = 0; c < nck; ++c) {
     const bool odd = c & 1;
@@ -890,21 +943,19 @@ __global__ __launch_bounds__(WM * WN * 64) void k_conv3(ConvArgs a, Batch g) {
     // (or segment 1's) into the other A buffer, which has two stages to arrive
     const T *anext = more ? abase0 + (c + 1) * CK : (SEG2 ? in1 + ((long long)by * w + bx) * a.cin2 : abase0);
     stage_dma<T, TM, TN, BN, CK, VEC, 3, NT, ANVD, BNV, true, ANVD>(
-        acc, Ac, Bx, pidx, 0, bcol, half, An, anext, arel, okbits, more ? a.cin : a.cin2, By,
-        wp0 + (c * 9 + 3) * wrow, boff, true, more || seg, wv, tid);
-    lds_barrier();
+        acc, fr, Ac, Bx, pidx, 0, bcol, half, An, anext, arel, okbits, more ? a.cin : a.cin2, By,
+        wp0 + (c * 9 + 3) * wrow, boff, true, more || seg, Ac, By, WP, true, wv, tid);
     // filter row 1 (y); prefetch row 2 into x (the halo patch lands with it)
     stage_dma<T, TM, TN, BN, CK, VEC, 3, NT, ANVD, BNV, false, 0>(
-        acc, Ac, By, pidx, WP, bcol, half, nullptr, nullptr, arel, okbits, 0, Bx, wp0 + (c * 9 + 6) * wrow, boff,
-        true, false, wv, tid);
-    lds_barrier();
-    // filter row 2 (x); prefetch the next chunk's row 0 (or segment 1's weights) into y
+        acc, fr, Ac, By, pidx, WP, bcol, half, nullptr, nullptr, arel, okbits, 0, Bx, wp0 + (c * 9 + 6) * wrow,
+        boff, true, false, Ac, Bx, 2 * WP, true, wv, tid);
+    // filter row 2 (x); prefetch the next chunk's row 0 (or segment 1's weights) into y;
+    // the next stage is the next chunk's row 0 or segment 1's first stage
     if (seg) dma_boff<T, NT, BNV, BN, CK, VEC>(boff, 1, a.cout_pad, n0, tid);
     const T *wnext = more ? wp0 + (c + 1) * 9 * wrow : wp1;
     stage_dma<T, TM, TN, BN, CK, VEC, 3, NT, ANVD, BNV, false, 0>(
-        acc, Ac, Bx, pidx, 2 * WP, bcol, half, nullptr, nullptr, arel, okbits, 0, By, wnext, boff, more || seg,
-        false, wv, tid);
-    lds_barrier();
+        acc, fr, Ac, Bx, pidx, 2 * WP, bcol, half, nullptr, nullptr, arel, okbits, 0, By, wnext, boff,
+        more || seg, false, An, By, more ? 0 : WP + 1, more || seg, wv, tid);
   }
   if constexpr (SEG2) {
     const T *abase1 = in1 + ((long long)by * w + bx) * a.cin2;
@@ -913,10 +964,9 @@ __global__ __launch_bounds__(WM * WN * 64) void k_conv3(ConvArgs a, Batch g) {
       const int st = 3 * nck + c2, ac = nck + c2;
       const bool more = c2 + 1 < nck2;
       stage_dma<T, TM, TN, BN, CK, VEC, 1, NT, ANVD, BNV, true, 0>(
-          acc, (ac & 1) ? A1 : A0, (st & 1) ? B1 : B0, pidx, WP + 1, bcol, half, (ac & 1) ? A0 : A1,
+          acc, fr, (ac & 1) ? A1 : A0, (st & 1) ? B1 : B0, pidx, WP + 1, bcol, half, (ac & 1) ? A0 : A1,
           abase1 + (c2 + 1) * CK, arel, okbits, a.cin2, (st & 1) ? B0 : B1, wp1 + (long long)(c2 + 1) * wrow,
-          boff, more, more, wv, tid);
-      lds_barrier();
+          boff, more, more, (ac & 1) ? A0 : A1, (st & 1) ? B0 : B1, WP + 1, more, wv, tid);
     }
   }
   if constexpr (EPI == EPI_STITCH) {
@@ -957,7 +1007,9 @@ static hipError_t run_conv3(const ConvArgs &a, const Batch &g, hipStream_t s) {
 //   im2col row of the 27 (filter tap, colour) values, zero-padded to 32, K = 32 runs on
 //   MFMA, and the LDS epilogue applies bias + ReLU and writes 16-byte rows of channels.
 // ---------------------------------------------------------------------------------------
-constexpr int kImgBlocksPerCU = 2;   // resident blocks per CU (registers: 2 waves per SIMD)
+// resident blocks per CU: BF16 three (LDS 3 x 50 KB, registers for 3 waves per SIMD),
+// FP32 two (its operands need more registers)
+template <typename T> constexpr int kImgBlocksPerCU = sizeof(T) == 2 ? 3 : 2;
 
 template <typename T>
 __device__ __forceinline__ void img_patch_load(float (&v)[4], const ConvArgs &a, const Batch &g, int patch,
@@ -980,7 +1032,7 @@ __device__ __forceinline__ void img_patch_load(float (&v)[4], const ConvArgs &a,
 }
 
 template <typename T>
-__global__ __launch_bounds__(256, kImgBlocksPerCU) void k_conv_img(ConvArgs a, Batch g) {
+__global__ __launch_bounds__(256, kImgBlocksPerCU<T>) void k_conv_img(ConvArgs a, Batch g) {
   constexpr int PH = 8, PW = 32, BM = 256, BN = 64, TM = 2, TN = 2, KP = 32;
   constexpr int HP = PH + 2, WP = PW + 2;               // image patch with its 1-pixel halo
   constexpr int RS = KP + 16 / (int)sizeof(T);         // LDS row stride (elements), 16 B pad
@@ -1151,7 +1203,7 @@ static hipError_t conv_dispatch(int in_mode, int epi, const ConvArgs &a, const B
       hipError_t e = hipGetDevice(&dev);
       if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
       if (e != hipSuccess) return e;
-      const int grid = std::min(nblk, kImgBlocksPerCU * ncu);
+      const int grid = std::min(nblk, kImgBlocksPerCU<T> * ncu);
       hipLaunchKernelGGL(k_conv_img<T>, dim3(grid), dim3(256), 0, s, a, g);
       return hipGetLastError();
     }
