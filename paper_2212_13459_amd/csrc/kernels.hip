@@ -721,7 +721,7 @@ __device__ __forceinline__ void dma_boff(unsigned (&boff)[BNV], int nrows, int c
 // (buffers An, Bn, offset toffn) into f[0], and then runs the second half of the MFMAs,
 // which cover the latency of those reads.
 template <typename T, int TM, int TN, int BN, int CK, int VEC, int NTAP, int NT, int ANVD, int BNV, bool DA,
-          int VMW>
+          int VMW, bool MIDA = false>
 __device__ __forceinline__ void stage_dma(f32x16 (&acc)[TM][TN], KFrag<TM, TN> (&f)[2], const T *__restrict__ A,
                                           const T *__restrict__ B, const int (&pidx)[TM], int toff0, int bcol,
                                           int half, T *__restrict__ adst, const T *abase,
@@ -781,7 +781,13 @@ __device__ __forceinline__ void stage_dma(f32x16 (&acc)[TM][TN], KFrag<TM, TN> (
       __builtin_amdgcn_s_waitcnt(0xc07f);
       lds_barrier();
       KFrag<TM, TN> keep = fl;   // f[0] is overwritten by the next stage's reads
-      if (has_next) load_kstep<T, TM, TN, BN, CK, VEC>(f[0], An, Bn, pidx, toffn, 0, 0, bcol, half);
+      if constexpr (MIDA) {
+        // single halo buffer: no wave reads it any more, so the next chunk's halo (adst,
+        // abase, cin, issue_a) goes out now; the caller waits for it
+        if (issue_a) dma_a<T, NT, ANVD, VEC>(adst, abase, arel, okbits, cin, wv, tid);
+      } else {
+        if (has_next) load_kstep<T, TM, TN, BN, CK, VEC>(f[0], An, Bn, pidx, toffn, 0, 0, bcol, half);
+      }
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int tm = TM / 2; tm < TM; ++tm)
@@ -836,8 +842,9 @@ __device__ __forceinline__ void stage_dma(f32x16 (&acc)[TM][TN], KFrag<TM, TN> (
   }
 }
 
-template <typename T, int BN, int WM, int WN, int PH, int EPI, bool SEG2, bool F32E>
-__global__ __launch_bounds__(WM * WN * 64) void k_conv3(ConvArgs a, Batch g) {
+// SA (single halo buffer) kernels are made to fit three resident blocks per CU
+template <typename T, int BN, int WM, int WN, int PH, int EPI, bool SEG2, bool F32E, bool SA>
+__global__ __launch_bounds__(WM * WN * 64, SA ? 3 : 1) void k_conv3(ConvArgs a, Batch g) {
   constexpr int PW = 32, BM = PH * PW;
   constexpr int NT = WM * WN * 64;
   constexpr int TM = BM / (WM * 32), TN = BN / (WN * 32);
@@ -850,10 +857,13 @@ __global__ __launch_bounds__(WM * WN * 64) void k_conv3(ConvArgs a, Batch g) {
   constexpr int AUNITS = ANVD * NT;                   // units written (every wave, padding included)
   constexpr int BNV = (3 * BN * 4 + NT - 1) / NT;
   constexpr int ASZ = AUNITS * VEC, BSZ = BNV * NT * VEC;
+  // SA: one halo buffer (more resident blocks per CU; the next chunk's halo is loaded
+  // between chunks, while the other blocks compute)
+  constexpr int NA = SA ? 1 : 2, SMEM = (NA * ASZ + 2 * BSZ) * (int)sizeof(T);
   static_assert(ANVD <= 32, "halo mask bits");
-  static_assert(epi_passes(BM, WN, TN, 2 * (ASZ + BSZ) * (int)sizeof(T)) > 0, "epilogue does not fit");
+  static_assert(epi_passes(BM, WN, TN, SMEM) > 0, "epilogue does not fit");
   constexpr bool WIDE = TM * TN >= 16;
-  __shared__ __attribute__((aligned(16))) T sm[2 * (ASZ + BSZ)];
+  __shared__ __attribute__((aligned(16))) T sm[NA * ASZ + 2 * BSZ];
   if constexpr (WIDE) asm volatile("" ::: "a0");
 
   // XCD-aware block order: workgroup L runs on XCD L mod 8, which takes the contiguous
@@ -920,7 +930,7 @@ __global__ __launch_bounds__(WM * WN * 64) void k_conv3(ConvArgs a, Batch g) {
   const T *abase0 = in0 + ((long long)by * w + bx) * a.cin;
   const long long wrow = (long long)a.cout_pad * CK;
 
-  T *const A0 = sm, *const A1 = sm + ASZ, *const B0 = sm + 2 * ASZ, *const B1 = sm + 2 * ASZ + BSZ;
+  T *const A0 = sm, *const A1 = sm + (NA - 1) * ASZ, *const B0 = sm + NA * ASZ, *const B1 = sm + NA * ASZ + BSZ;
   dma_a<T, NT, ANVD, VEC>(A0, abase0, arel, okbits, a.cin, wv, tid);
   dma_b<T, NT, BNV, VEC>(B0, wp0, boff, wv);
   __builtin_amdgcn_s_waitcnt(0);
@@ -932,6 +942,47 @@ __global__ __launch_bounds__(WM * WN * 64) void k_conv3(ConvArgs a, Batch g) {
   // fragments in fr[0]
   KFrag<TM, TN> fr[2];
   load_kstep<T, TM, TN, BN, CK, VEC>(fr[0], A0, B0, pidx, 0, 0, 0, bcol, half);
+  if constexpr (SA) {
+    // one halo buffer A0: each chunk's last stage issues the next halo chunk (or segment
+    // 1's first) halfway through its last k-step; the wait and barrier follow the stage
+#pragma unroll 1
+    for (int c = 0; c < nck; ++c) {
+      const bool odd = c & 1;
+      T *const Bx = odd ? B1 : B0, *const By = odd ? B0 : B1;
+      const bool more = c + 1 < nck;
+      const bool seg = !more && SEG2 && nck2 > 0;
+      stage_dma<T, TM, TN, BN, CK, VEC, 3, NT, ANVD, BNV, false, 0>(
+          acc, fr, A0, Bx, pidx, 0, bcol, half, nullptr, nullptr, arel, okbits, 0, By, wp0 + (c * 9 + 3) * wrow,
+          boff, true, false, A0, By, WP, true, wv, tid);
+      stage_dma<T, TM, TN, BN, CK, VEC, 3, NT, ANVD, BNV, false, 0>(
+          acc, fr, A0, By, pidx, WP, bcol, half, nullptr, nullptr, arel, okbits, 0, Bx, wp0 + (c * 9 + 6) * wrow,
+          boff, true, false, A0, Bx, 2 * WP, true, wv, tid);
+      if (seg) dma_boff<T, NT, BNV, BN, CK, VEC>(boff, 1, a.cout_pad, n0, tid);
+      const T *wnext = more ? wp0 + (c + 1) * 9 * wrow : wp1;
+      const T *anext = more ? abase0 + (c + 1) * CK : (SEG2 ? in1 + ((long long)by * w + bx) * a.cin2 : abase0);
+      stage_dma<T, TM, TN, BN, CK, VEC, 3, NT, ANVD, BNV, false, 0, true>(
+          acc, fr, A0, Bx, pidx, 2 * WP, bcol, half, A0, anext, arel, okbits, more ? a.cin : a.cin2, By, wnext, boff,
+          more || seg, more || seg, A0, By, 0, false, wv, tid);
+      __builtin_amdgcn_s_waitcnt(0);
+      lds_barrier();
+      if (more || seg) load_kstep<T, TM, TN, BN, CK, VEC>(fr[0], A0, By, pidx, more ? 0 : WP + 1, 0, 0, bcol, half);
+    }
+    if constexpr (SEG2) {
+      const T *abase1 = in1 + ((long long)by * w + bx) * a.cin2;
+#pragma unroll 1
+      for (int c2 = 0; c2 < nck2; ++c2) {
+        const int st = 3 * nck + c2;
+        const bool more = c2 + 1 < nck2;
+        stage_dma<T, TM, TN, BN, CK, VEC, 1, NT, ANVD, BNV, false, 0, true>(
+            acc, fr, A0, (st & 1) ? B1 : B0, pidx, WP + 1, bcol, half, A0, abase1 + (c2 + 1) * CK, arel, okbits,
+            a.cin2, (st & 1) ? B0 : B1, wp1 + (long long)(c2 + 1) * wrow, boff, more, more, A0, B0, 0, false, wv,
+            tid);
+        __builtin_amdgcn_s_waitcnt(0);
+        lds_barrier();
+        if (more) load_kstep<T, TM, TN, BN, CK, VEC>(fr[0], A0, (st & 1) ? B0 : B1, pidx, WP + 1, 0, 0, bcol, half);
+      }
+    }
+  } else {
 #pragma unroll 1
   for (int c = 0; c < nck; ++c) {
     const bool odd = c & 1;
@@ -969,6 +1020,7 @@ __global__ __launch_bounds__(WM * WN * 64) void k_conv3(ConvArgs a, Batch g) {
           boff, more, more, (ac & 1) ? A0 : A1, (st & 1) ? B0 : B1, WP + 1, more, wv, tid);
     }
   }
+  }
   if constexpr (EPI == EPI_STITCH) {
     // image gradient (FP32 CHW) at the owned pixels: channels 0..2 of the padded 32
     // accumulator element r of lanes 0..31 is channel r of pixel l32 (see mma_kstep)
@@ -983,18 +1035,18 @@ __global__ __launch_bounds__(WM * WN * 64) void k_conv3(ConvArgs a, Batch g) {
       }
     }
   } else {
-    conv_epilogue<T, BN, WM, WN, PH, EPI, 2 * (ASZ + BSZ) * (int)sizeof(T), F32E>(acc, sm, a, g, t, slot, y0, x0,
-                                                                                h, w, n0, tid, wm, wn, l32, half);
+    conv_epilogue<T, BN, WM, WN, PH, EPI, SMEM, F32E>(acc, sm, a, g, t, slot, y0, x0, h, w, n0, tid, wm, wn, l32,
+                                                      half);
   }
 }
 
-template <typename T, int BN, int WM, int WN, int PH, int EPI, bool SEG2, bool F32E = false>
+template <typename T, int BN, int WM, int WN, int PH, int EPI, bool SEG2, bool F32E = false, bool SA = false>
 static hipError_t run_conv3(const ConvArgs &a, const Batch &g, hipStream_t s) {
   const int nblk = g.pfx[g.n];
   if (nblk == 0) return hipSuccess;
   // one-dimensional grid in XCD-aware order (see k_conv3)
   dim3 grid(8 * ((nblk + 7) / 8) * ((a.cout + BN - 1) / BN));
-  hipLaunchKernelGGL((k_conv3<T, BN, WM, WN, PH, EPI, SEG2, F32E>), grid, dim3(WM * WN * 64), 0, s, a, g);
+  hipLaunchKernelGGL((k_conv3<T, BN, WM, WN, PH, EPI, SEG2, F32E, SA>), grid, dim3(WM * WN * 64), 0, s, a, g);
   return hipGetLastError();
 }
 
@@ -1156,16 +1208,18 @@ static hipError_t run_conv(const ConvArgs &a, const Batch &g, hipStream_t s) {
 // accumulators, one wave per SIMD, long K loops); narrower layers have short K loops
 // whose staging latency a second wave per SIMD hides better, so they keep 2 waves per
 // SIMD, as FP32 does throughout.
-struct Conv2Cfg { int bn, wm, wn, ph; };
+// 64-channel layers (K loops of only 2 chunks, so per-block set-up and epilogue weigh
+// most) use one halo buffer: 52 KB of LDS, three resident blocks per CU.
+struct Conv2Cfg { int bn, wm, wn, ph; bool sa; };
 static Conv2Cfg conv2_cfg(int precision, int cout) {
   if (precision == 1) {
-    if (cout <= 64) return {64, 4, 1, 8};
-    if (cout % 256 == 0) return {256, 2, 2, 8};
-    return {128, 4, 2, 8};
+    if (cout <= 64) return {64, 4, 1, 8, true};
+    if (cout % 256 == 0) return {256, 2, 2, 8, false};
+    return {128, 4, 2, 8, false};
   }
-  if (cout <= 64) return {64, 4, 1, 8};
-  if (cout % 256 == 0) return {256, 2, 4, 8};
-  return {128, 4, 2, 8};
+  if (cout <= 64) return {64, 4, 1, 8, true};
+  if (cout % 256 == 0) return {256, 2, 4, 8, false};
+  return {128, 4, 2, 8, false};
 }
 
 int conv_block_rows(int precision, int in_mode, int epi, int cout) {
@@ -1210,43 +1264,39 @@ static hipError_t conv_dispatch(int in_mode, int epi, const ConvArgs &a, const B
     if (in_mode != IN_NHWC) return hipErrorInvalidValue;
     if constexpr (sizeof(T) == 2) {
       // F32E: the content layer's FP32 residual needs the FP32 epilogue
-#define NST_CONV3_FWD(BN_, WM_, WN_, PH_)                                                  \
-  return a.rc ? run_conv3<T, BN_, WM_, WN_, PH_, EPI_FWD, false, true>(a, g, s)          \
-              : run_conv3<T, BN_, WM_, WN_, PH_, EPI_FWD, false, false>(a, g, s)
-      if (small) NST_CONV3_FWD(64, 4, 1, 8);
-      if (a.cout % 256 == 0) NST_CONV3_FWD(256, 2, 2, 8);
-      NST_CONV3_FWD(128, 4, 2, 8);
+#define NST_CONV3_FWD(BN_, WM_, WN_, PH_, SA_)                                             \
+  return a.rc ? run_conv3<T, BN_, WM_, WN_, PH_, EPI_FWD, false, true, SA_>(a, g, s)     \
+              : run_conv3<T, BN_, WM_, WN_, PH_, EPI_FWD, false, false, SA_>(a, g, s)
+      if (small) NST_CONV3_FWD(64, 4, 1, 8, true);
+      if (a.cout % 256 == 0) NST_CONV3_FWD(256, 2, 2, 8, false);
+      NST_CONV3_FWD(128, 4, 2, 8, false);
 #undef NST_CONV3_FWD
     } else {
-      if (small) return run_conv3<T, 64, 4, 1, 8, EPI_FWD, false>(a, g, s);
+      if (small) return run_conv3<T, 64, 4, 1, 8, EPI_FWD, false, false, true>(a, g, s);
       if (a.cout % 256 == 0) return run_conv3<T, 256, 2, 4, 8, EPI_FWD, false>(a, g, s);
       return run_conv3<T, 128, 4, 2, 8, EPI_FWD, false>(a, g, s);
     }
   }
   // EPI_BWD
   if (in_mode == IN_NHWC) {
-#define NST_CONV3_BWD(BN_, WM_, WN_, PH_)                                                  \
-  return seg2 ? run_conv3<T, BN_, WM_, WN_, PH_, EPI_BWD, true>(a, g, s)                  \
-              : run_conv3<T, BN_, WM_, WN_, PH_, EPI_BWD, false>(a, g, s)
-#define NST_CONV3_BWD_RC(BN_, WM_, WN_, PH_)                                               \
-  return seg2 ? run_conv3<T, BN_, WM_, WN_, PH_, EPI_BWD, true, true>(a, g, s)            \
-              : run_conv3<T, BN_, WM_, WN_, PH_, EPI_BWD, false, true>(a, g, s)
+#define NST_CONV3_BWD(BN_, WM_, WN_, PH_, RC_, SA_)                                        \
+  return seg2 ? run_conv3<T, BN_, WM_, WN_, PH_, EPI_BWD, true, RC_, SA_>(a, g, s)        \
+              : run_conv3<T, BN_, WM_, WN_, PH_, EPI_BWD, false, RC_, SA_>(a, g, s)
     if constexpr (sizeof(T) == 2) {
       if (a.rc) {   // the content residual enters in FP32 (F32E)
-        if (small) NST_CONV3_BWD_RC(64, 4, 1, 8);
-        if (a.cout % 256 == 0) NST_CONV3_BWD_RC(256, 2, 2, 8);
-        NST_CONV3_BWD_RC(128, 4, 2, 8);
+        if (small) NST_CONV3_BWD(64, 4, 1, 8, true, true);
+        if (a.cout % 256 == 0) NST_CONV3_BWD(256, 2, 2, 8, true, false);
+        NST_CONV3_BWD(128, 4, 2, 8, true, false);
       }
-      if (small) NST_CONV3_BWD(64, 4, 1, 8);
-      if (a.cout % 256 == 0) NST_CONV3_BWD(256, 2, 2, 8);
-      NST_CONV3_BWD(128, 4, 2, 8);
+      if (small) NST_CONV3_BWD(64, 4, 1, 8, false, true);
+      if (a.cout % 256 == 0) NST_CONV3_BWD(256, 2, 2, 8, false, false);
+      NST_CONV3_BWD(128, 4, 2, 8, false, false);
     } else {
-      if (small) NST_CONV3_BWD(64, 4, 1, 8);
-      if (a.cout % 256 == 0) NST_CONV3_BWD(256, 2, 4, 8);
-      NST_CONV3_BWD(128, 4, 2, 8);
+      if (small) NST_CONV3_BWD(64, 4, 1, 8, false, true);
+      if (a.cout % 256 == 0) NST_CONV3_BWD(256, 2, 4, 8, false, false);
+      NST_CONV3_BWD(128, 4, 2, 8, false, false);
     }
 #undef NST_CONV3_BWD
-#undef NST_CONV3_BWD_RC
   }
   if (in_mode == IN_NONE) {
     if (small)
@@ -1271,13 +1321,13 @@ const char *conv_kernel_name(int precision, int in_mode, int epi, const ConvArgs
   if (in_mode == IN_NHWC && epi != EPI_STITCH) {
     const Conv2Cfg k = conv2_cfg(precision, a.cout);
     const bool f32e = precision == 1 && a.rc != nullptr;
-    snprintf(o, 160, "void nst::k_conv3<%s, %d, %d, %d, %d, %d, %s, %s>(nst::ConvArgs, nst::Batch)",
+    snprintf(o, 160, "void nst::k_conv3<%s, %d, %d, %d, %d, %d, %s, %s, %s>(nst::ConvArgs, nst::Batch)",
              precision == 1 ? "__bf16" : "float", k.bn, k.wm, k.wn, k.ph, epi, seg2 ? "true" : "false",
-             f32e ? "true" : "false");
+             f32e ? "true" : "false", k.sa ? "true" : "false");
     return o;
   }
   if (epi == EPI_STITCH) {
-    snprintf(o, 160, "void nst::k_conv3<%s, 32, 4, 1, 8, %d, false, false>(nst::ConvArgs, nst::Batch)",
+    snprintf(o, 160, "void nst::k_conv3<%s, 32, 4, 1, 8, %d, false, false, false>(nst::ConvArgs, nst::Batch)",
              precision == 1 ? "__bf16" : "float", EPI_STITCH);
     return o;
   } else if (a.cout <= 64) {
