@@ -1244,7 +1244,7 @@ static hipError_t conv_dispatch(int in_mode, int epi, const ConvArgs &a, const B
   const bool seg2 = a.in2 != nullptr && a.cin2 > 0;
   if (epi == EPI_STITCH) {
     if (in_mode != IN_NHWC || seg2 || a.cout > 3 || a.cout_pad != 32) return hipErrorInvalidValue;
-    return run_conv3<T, 32, 4, 1, 8, EPI_STITCH, false>(a, g, s);
+    return run_conv3<T, 32, 4, 1, 8, EPI_STITCH, false, false, true>(a, g, s);   // one halo buffer
   }
   const bool small = a.cout <= 64;
   if (epi == EPI_FWD) {
@@ -1327,7 +1327,7 @@ const char *conv_kernel_name(int precision, int in_mode, int epi, const ConvArgs
     return o;
   }
   if (epi == EPI_STITCH) {
-    snprintf(o, 160, "void nst::k_conv3<%s, 32, 4, 1, 8, %d, false, false, false>(nst::ConvArgs, nst::Batch)",
+    snprintf(o, 160, "void nst::k_conv3<%s, 32, 4, 1, 8, %d, false, false, true>(nst::ConvArgs, nst::Batch)",
              precision == 1 ? "__bf16" : "float", EPI_STITCH);
     return o;
   } else if (a.cout <= 64) {
