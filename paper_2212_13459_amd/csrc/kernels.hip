@@ -842,9 +842,10 @@ __device__ __forceinline__ void stage_dma(f32x16 (&acc)[TM][TN], KFrag<TM, TN> (
   }
 }
 
-// SA (single halo buffer) kernels are made to fit three resident blocks per CU
+// SA (single halo buffer) kernels are made to fit several resident blocks per CU: three
+// for 64-channel tiles, two for 128-channel ones
 template <typename T, int BN, int WM, int WN, int PH, int EPI, bool SEG2, bool F32E, bool SA>
-__global__ __launch_bounds__(WM * WN * 64, SA ? 3 : 1) void k_conv3(ConvArgs a, Batch g) {
+__global__ __launch_bounds__(WM * WN * 64, SA ? (BN <= 64 ? 3 : 2) : 1) void k_conv3(ConvArgs a, Batch g) {
   constexpr int PW = 32, BM = PH * PW;
   constexpr int NT = WM * WN * 64;
   constexpr int TM = BM / (WM * 32), TN = BN / (WN * 32);
@@ -1208,14 +1209,15 @@ static hipError_t run_conv(const ConvArgs &a, const Batch &g, hipStream_t s) {
 // accumulators, one wave per SIMD, long K loops); narrower layers have short K loops
 // whose staging latency a second wave per SIMD hides better, so they keep 2 waves per
 // SIMD, as FP32 does throughout.
-// 64-channel layers (K loops of only 2 chunks, so per-block set-up and epilogue weigh
-// most) use one halo buffer: 52 KB of LDS, three resident blocks per CU.
+// Narrow layers have short K loops (2 to 4 chunks), so per-block set-up and epilogue
+// weigh most: they use one halo buffer, 64-channel tiles with three resident blocks per
+// CU (52 KB of LDS), BF16 128-channel tiles (4 waves of 128 px x 64 ch) with two (76 KB).
 struct Conv2Cfg { int bn, wm, wn, ph; bool sa; };
 static Conv2Cfg conv2_cfg(int precision, int cout) {
   if (precision == 1) {
     if (cout <= 64) return {64, 4, 1, 8, true};
     if (cout % 256 == 0) return {256, 2, 2, 8, false};
-    return {128, 4, 2, 8, false};
+    return {128, 2, 2, 8, true};
   }
   if (cout <= 64) return {64, 4, 1, 8, true};
   if (cout % 256 == 0) return {256, 2, 4, 8, false};
@@ -1269,7 +1271,7 @@ static hipError_t conv_dispatch(int in_mode, int epi, const ConvArgs &a, const B
               : run_conv3<T, BN_, WM_, WN_, PH_, EPI_FWD, false, false, SA_>(a, g, s)
       if (small) NST_CONV3_FWD(64, 4, 1, 8, true);
       if (a.cout % 256 == 0) NST_CONV3_FWD(256, 2, 2, 8, false);
-      NST_CONV3_FWD(128, 4, 2, 8, false);
+      NST_CONV3_FWD(128, 2, 2, 8, true);
 #undef NST_CONV3_FWD
     } else {
       if (small) return run_conv3<T, 64, 4, 1, 8, EPI_FWD, false, false, true>(a, g, s);
@@ -1286,11 +1288,11 @@ static hipError_t conv_dispatch(int in_mode, int epi, const ConvArgs &a, const B
       if (a.rc) {   // the content residual enters in FP32 (F32E)
         if (small) NST_CONV3_BWD(64, 4, 1, 8, true, true);
         if (a.cout % 256 == 0) NST_CONV3_BWD(256, 2, 2, 8, true, false);
-        NST_CONV3_BWD(128, 4, 2, 8, true, false);
+        NST_CONV3_BWD(128, 2, 2, 8, true, true);
       }
       if (small) NST_CONV3_BWD(64, 4, 1, 8, false, true);
       if (a.cout % 256 == 0) NST_CONV3_BWD(256, 2, 2, 8, false, false);
-      NST_CONV3_BWD(128, 4, 2, 8, false, false);
+      NST_CONV3_BWD(128, 2, 2, 8, false, true);
     } else {
       if (small) NST_CONV3_BWD(64, 4, 1, 8, false, true);
       if (a.cout % 256 == 0) NST_CONV3_BWD(256, 2, 4, 8, false, false);
