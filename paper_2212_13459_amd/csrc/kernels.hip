@@ -245,9 +245,11 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a, Batch g) {
 //   the 3 taps of one filter row for BN channels in LDS, and the first stage of a chunk
 //   also the (PH + 2) x 34 halo patch of that chunk.  Stages are double-buffered and
 //   filled by LDS DMA (global_load_lds_dwordx4: each lane's 16 bytes go straight to LDS
-//   at the wave's base + 16 x lane, no registers or LDS store instructions involved), so
-//   the next stage's loads are in flight during the whole current stage; a stage ends
-//   with a wait for the wave's own loads and one barrier.
+//   at the wave's base + 16 x lane, no registers or LDS store instructions involved): the
+//   next stage's loads are issued between the current stage's first MFMAs and are in
+//   flight during the rest of it; halfway through its last k-step a stage waits for the
+//   wave's own loads and passes one barrier.  With one halo buffer (SA) the next chunk's
+//   halo is loaded between chunks instead.
 //   A 32-row MFMA operand block is one patch row of 32 pixels, i.e. 32 consecutive LDS
 //   rows, which gfx950 reads without bank conflicts (blocks of 2 x 16 rows with a gap
 //   between them, as a 16-wide patch gives, read at half rate).  Halo-patch rows are
@@ -1204,14 +1206,13 @@ static hipError_t run_conv(const ConvArgs &a, const Batch &g, hipStream_t s) {
   return hipGetLastError();
 }
 
-// k_conv3 tile configurations: BN output channels, WM x WN waves, PH x 32 pixel patches.
-// BF16 layers with 256 or 512 channels use 4 waves with 128 x 128 wave tiles (AGPR
-// accumulators, one wave per SIMD, long K loops); narrower layers have short K loops
-// whose staging latency a second wave per SIMD hides better, so they keep 2 waves per
-// SIMD, as FP32 does throughout.
-// Narrow layers have short K loops (2 to 4 chunks), so per-block set-up and epilogue
-// weigh most: they use one halo buffer, 64-channel tiles with three resident blocks per
-// CU (52 KB of LDS), BF16 128-channel tiles (4 waves of 128 px x 64 ch) with two (76 KB).
+// k_conv3 tile configurations: BN output channels, WM x WN waves, PH x 32 pixel patches,
+// sa = one halo buffer.  BF16 layers with 256 or 512 channels (long K loops) use 4 waves
+// with 128 x 128 wave tiles (AGPR accumulators, one block and one wave per SIMD).
+// Narrower layers have short K loops (2 to 4 chunks), so per-block set-up and epilogue
+// weigh most: they use one halo buffer and several resident blocks per CU, whose phases
+// overlap: 64-channel tiles with three (52 KB of LDS), BF16 128-channel tiles (4 waves of
+// 128 px x 64 ch) with two (76 KB).  FP32 keeps two waves per SIMD throughout.
 struct Conv2Cfg { int bn, wm, wn, ph; bool sa; };
 static Conv2Cfg conv2_cfg(int precision, int cout) {
   if (precision == 1) {
