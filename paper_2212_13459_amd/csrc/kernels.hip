@@ -1618,18 +1618,8 @@ __global__ __launch_bounds__(256) void k_gram_tile_reduce(const float *part, lon
   const int ii = min(i, j), jj = max(i, j);
   const int nch = g.pfx[t + 1] - g.pfx[t];
   const float *p = part + g.slot[t] * part_ss + (long long)ii * C + jj;
-  const long long cc = (long long)C * C;
   double s = 0.0;
-  // chunk order as written; the loads of 8 chunks go out together
-  int k = 0;
-  for (; k + 8 <= nch; k += 8) {
-    float v[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) v[q] = p[(k + q) * cc];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) s += (double)v[q];
-  }
-  for (; k < nch; ++k) s += (double)p[k * cc];
+  for (int k = 0; k < nch; ++k) s += (double)p[(long long)k * C * C];
   tilesum[(long long)t * C * C + e] = s;
 }
 
