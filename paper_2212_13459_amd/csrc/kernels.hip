@@ -1623,6 +1623,31 @@ __global__ __launch_bounds__(256) void k_gram_tile_reduce(const float *part, lon
   tilesum[(long long)t * C * C + e] = s;
 }
 
+// The same sums over 32 x 32 output tiles with coalesced loads: thread (ty, tx) of an
+// output tile sums, in chunk order, the partial at row ty, column tx of the upper-triangle
+// tile that holds the tile or its mirror image; through LDS the lower-triangle outputs
+// take the transposed sums.  Every output element gets the same sequence of additions as
+// above; for C not a multiple of 32 the kernel above is used.
+__global__ __launch_bounds__(1024) void k_gram_tile_reduce32(const float *part, long long part_ss, int C,
+                                                             Batch g, double *tilesum) {
+  __shared__ double sm[32][33];
+  const int t = blockIdx.y;
+  const int nb = C / 32;
+  const int bi = blockIdx.x / nb, bj = blockIdx.x - (blockIdx.x / nb) * nb;
+  const int si = min(bi, bj), sj = max(bi, bj);
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const int nch = g.pfx[t + 1] - g.pfx[t];
+  const long long cc = (long long)C * C;
+  const float *q = part + g.slot[t] * part_ss + (long long)(si * 32 + ty) * C + sj * 32 + tx;
+  double s = 0.0;
+  for (int k = 0; k < nch; ++k) s += (double)q[k * cc];
+  sm[ty][tx] = s;   // sum of part[.][si 32 + ty][sj 32 + tx]
+  __syncthreads();
+  // output (i, j) = (bi 32 + ty, bj 32 + tx) needs part[min(i, j)][max(i, j)]
+  const double v = bi < bj ? sm[ty][tx] : bi > bj ? sm[tx][ty] : (ty <= tx ? sm[ty][tx] : sm[tx][ty]);
+  tilesum[(long long)t * cc + (long long)(bi * 32 + ty) * C + bj * 32 + tx] = v;
+}
+
 __global__ __launch_bounds__(256) void k_gram_accum(const double *tilesum, int n_tiles, int CC,
                                                     double *gacc) {
   const int e = blockIdx.x * 256 + threadIdx.x;
@@ -1661,8 +1686,13 @@ hipError_t launch_gram(int precision, const void *act, long long act_ss, int C, 
 hipError_t launch_gram_tile_reduce(const float *part, long long part_ss, int C, const Batch &g,
                                    double *tilesum, hipStream_t s) {
   if (g.n == 0) return hipSuccess;
-  dim3 grid((C * C + 255) / 256, g.n);
-  hipLaunchKernelGGL(k_gram_tile_reduce, grid, dim3(256), 0, s, part, part_ss, C, g, tilesum);
+  if (C % 32 == 0) {
+    dim3 grid((C / 32) * (C / 32), g.n);
+    hipLaunchKernelGGL(k_gram_tile_reduce32, grid, dim3(1024), 0, s, part, part_ss, C, g, tilesum);
+  } else {
+    dim3 grid((C * C + 255) / 256, g.n);
+    hipLaunchKernelGGL(k_gram_tile_reduce, grid, dim3(256), 0, s, part, part_ss, C, g, tilesum);
+  }
   return hipGetLastError();
 }
 
