@@ -1742,7 +1742,17 @@ __global__ void k_content_accum(const double *part, long long part_ss, Batch g, 
   double s = acc[0];
   for (int t = 0; t < g.n; ++t) {
     const int nb = g.pfx[t + 1] - g.pfx[t];
-    for (int b = 0; b < nb; ++b) s += part[g.slot[t] * part_ss + b];
+    const double *p = part + g.slot[t] * part_ss;
+    // in block order; the loads of 8 blocks go out together
+    int b = 0;
+    for (; b + 8 <= nb; b += 8) {
+      double v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = p[b + q];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) s += v[q];
+    }
+    for (; b < nb; ++b) s += p[b];
   }
   acc[0] = s;
 }
@@ -1828,27 +1838,39 @@ hipError_t launch_gram_normalize(const double *gacc, double *g, size_t n, double
   return hipGetLastError();
 }
 
-// Style energy terms and the packed residual operand, one workgroup per style layer.
+// Style energy terms, one workgroup per style layer, and the packed residual operand,
+// one thread per element:
 //   e_style[l] = w_l sum_ij (G - Ghat)_ij^2                      (Eq. 3)
 //   B[k = i][n = j] = (2 w_l / n_p) (D_ij + D_ji), D = G - Ghat   (Table 1, Gram row)
-// packed as [i / CK][j][i mod CK] in compute precision.
-template <typename T>
-__global__ __launch_bounds__(256) void k_style_terms(const double *g, const double *gt,
-                                                     StyleTermsArgs a, T *dt, double *e_style) {
+// packed as [i / CK][j][i mod CK] in compute precision.  Each energy sum runs over the
+// elements in a fixed order (thread stride, then a tree over the workgroup).
+__global__ __launch_bounds__(256) void k_style_energy(const double *g, const double *gt, StyleTermsArgs a,
+                                                      double *e_style) {
   __shared__ double red[256];
   const int l = blockIdx.x;
   const int C = a.C[l];
-  constexpr int CK = Tr<T>::CK;
   const double *G = g + a.off[l], *H = gt + a.off[l];
-  T *D = dt + a.dt_off[l];
-  const double coef = 2.0 * a.w[l] * a.inv_np[l];
   double s = 0.0;
-  for (int e = threadIdx.x; e < C * C; e += 256) {
-    const int i = e / C, j = e - i * C;
+  // elements e = tid + 256 m in order of m; the loads of 8 consecutive m go out together
+  // (a few workgroups only: the latency of one load per step would not be hidden)
+  const int CC = C * C;
+  int e = threadIdx.x;
+  for (; e + 7 * 256 < CC; e += 8 * 256) {
+    double gv[8], hv[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      gv[q] = G[e + q * 256];
+      hv[q] = H[e + q * 256];
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const double dij = gv[q] - hv[q];
+      s += dij * dij;
+    }
+  }
+  for (; e < CC; e += 256) {
     const double dij = G[e] - H[e];
-    const double dji = G[(long long)j * C + i] - H[(long long)j * C + i];
     s += dij * dij;
-    D[((long long)(i / CK) * C + j) * CK + (i % CK)] = from_f<T>((float)(coef * (dij + dji)));
   }
   red[threadIdx.x] = s;
   __syncthreads();
@@ -1859,15 +1881,39 @@ __global__ __launch_bounds__(256) void k_style_terms(const double *g, const doub
   if (threadIdx.x == 0) e_style[l] = a.w[l] * red[0];
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void k_style_pack(const double *g, const double *gt, StyleTermsArgs a, T *dt) {
+  constexpr int CK = Tr<T>::CK;
+  const int l = blockIdx.y;
+  const int C = a.C[l];
+  const long long u = (long long)blockIdx.x * 256 + threadIdx.x;   // packed index
+  if (u >= (long long)((C + CK - 1) / CK) * C * CK) return;
+  const int i_lo = (int)(u % CK);
+  const long long r = u / CK;
+  const int j = (int)(r % C), i = (int)(r / C) * CK + i_lo;
+  if (i >= C) return;
+  const double *G = g + a.off[l], *H = gt + a.off[l];
+  const double coef = 2.0 * a.w[l] * a.inv_np[l];
+  const double dij = G[(long long)i * C + j] - H[(long long)i * C + j];
+  const double dji = G[(long long)j * C + i] - H[(long long)j * C + i];
+  dt[a.dt_off[l] + u] = from_f<T>((float)(coef * (dij + dji)));
+}
+
 hipError_t launch_style_terms(int precision, const double *g, const double *gt,
                               const StyleTermsArgs &a, void *dt, double *e_style, hipStream_t s) {
   if (a.n_style == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_style_energy, dim3(a.n_style), dim3(256), 0, s, g, gt, a, e_style);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int ck = precision == 1 ? Tr<bf16>::CK : Tr<float>::CK;
+  long long most = 0;
+  for (int l = 0; l < a.n_style; ++l)
+    most = std::max(most, (long long)((a.C[l] + ck - 1) / ck) * a.C[l] * ck);
+  const dim3 grid((unsigned)((most + 255) / 256), a.n_style);
   if (precision == 1)
-    hipLaunchKernelGGL(k_style_terms<bf16>, dim3(a.n_style), dim3(256), 0, s, g, gt, a,
-                       (bf16 *)dt, e_style);
+    hipLaunchKernelGGL(k_style_pack<bf16>, grid, dim3(256), 0, s, g, gt, a, (bf16 *)dt);
   else
-    hipLaunchKernelGGL(k_style_terms<float>, dim3(a.n_style), dim3(256), 0, s, g, gt, a,
-                       (float *)dt, e_style);
+    hipLaunchKernelGGL(k_style_pack<float>, grid, dim3(256), 0, s, g, gt, a, (float *)dt);
   return hipGetLastError();
 }
 
