@@ -173,7 +173,7 @@ def main():
     if args.gpus != 1 or world != 1:
         print("bench.py: this implementation runs on one GPU; --gpus N with N > 1 is not supported "
               "(the tiles of one evaluation would shard across GPUs with one Gram all-reduce, which "
-              "this build does not implement)", file=sys.stderr)
+              "is not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import torch
