@@ -1719,13 +1719,25 @@ __global__ __launch_bounds__(256) void k_content_partial(const float *rc, long l
   const int ow = c1 - c0, npx = (r1 - r0) * ow;
   const float *b = rc + g.slot[t] * rc_ss;
   double s = 0.0;
+  // element e = pl C + c, e = tid + 256 m in order of m; pixel pl and channel c advance
+  // incrementally and the pixel's address is recomputed only when pl changes
+  int pl = threadIdx.x / C, c = threadIdx.x - pl * C;
+  int cur = -1;
+  const float *row = b;
   for (int e = threadIdx.x; e < kContentBlockPx * C; e += 256) {
-    const int pl = e / C, c = e - pl * C;
     const int q = blk * kContentBlockPx + pl;
     if (q < npx) {
-      const int y = r0 + q / ow, x = c0 + q % ow;
-      const double d = b[((long long)y * w + x) * C + c];
+      if (pl != cur) {
+        cur = pl;
+        row = b + ((long long)(r0 + q / ow) * w + (c0 + q % ow)) * C;
+      }
+      const double d = row[c];
       s += d * d;
+    }
+    c += 256;
+    while (c >= C) {
+      c -= C;
+      ++pl;
     }
   }
   red[threadIdx.x] = s;
