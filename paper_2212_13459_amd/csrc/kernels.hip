@@ -1755,14 +1755,14 @@ __global__ void k_content_accum(const double *part, long long part_ss, Batch g, 
   for (int t = 0; t < g.n; ++t) {
     const int nb = g.pfx[t + 1] - g.pfx[t];
     const double *p = part + g.slot[t] * part_ss;
-    // in block order; the loads of 8 blocks go out together
+    // in block order; the loads of 32 blocks go out together
     int b = 0;
-    for (; b + 8 <= nb; b += 8) {
-      double v[8];
+    for (; b + 32 <= nb; b += 32) {
+      double v[32];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) v[q] = p[b + q];
+      for (int q = 0; q < 32; ++q) v[q] = p[b + q];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) s += v[q];
+      for (int q = 0; q < 32; ++q) s += v[q];
     }
     for (; b < nb; ++b) s += p[b];
   }
