@@ -1495,11 +1495,12 @@ __global__ __launch_bounds__(256) void k_gram(const T *act, long long act_ss, in
 // BF16 Gram partials: same chunks and output layout as k_gram, on bf16 MFMA.  A stage of
 // 64 owned pixels is written channel-major into LDS (row = channel, 64 pixels + pad), so
 // that each lane's operand is 8 consecutive pixels of one channel; products are exact in
-// FP32 and accumulate in FP32 within the chunk.  Stages are double-buffered (one barrier
-// per stage, the next stage's loads in registers during the MFMAs).  Block CB x CB of
+// FP32 and accumulate in FP32 within the chunk.  One LDS stage buffer (the next stage's
+// loads are in registers during the MFMAs; a second barrier per stage guards the buffer),
+// so that three workgroups fit on a CU and keep more loads in flight.  Block CB x CB of
 // the Gram per workgroup, 4 waves in 2 x 2.
 template <int CB>
-__global__ __launch_bounds__(256) void k_gram_bf16(const bf16 *act, long long act_ss, int C,
+__global__ __launch_bounds__(256, 3) void k_gram_bf16(const bf16 *act, long long act_ss, int C,
                                                    Batch g, float *part, long long part_ss) {
   constexpr int SP = 64, RS = SP + 8;                  // pixels per stage, LDS row stride
   constexpr int TB = CB / 64;                           // 32x32 blocks per wave per dim
@@ -1509,10 +1510,10 @@ __global__ __launch_bounds__(256) void k_gram_bf16(const bf16 *act, long long ac
   constexpr int NI = (SP / 2) * (CB / 8);               // items per operand per stage
   constexpr int PT = 2 * NI / 256;                      // items per thread (both operands)
   static_assert((2 * NI) % 256 == 0 && SP == 64, "stage items per thread");
-  // double-buffered channel-major stages: the next stage's loads are in registers while
-  // the MFMAs of the current one run
-  __shared__ __attribute__((aligned(16))) bf16 At[2][CB * RS];
-  __shared__ __attribute__((aligned(16))) bf16 Bt[2][CB * RS];
+  // channel-major stage: the next stage's loads are in registers while the MFMAs of the
+  // current one run
+  __shared__ __attribute__((aligned(16))) bf16 At[1][CB * RS];
+  __shared__ __attribute__((aligned(16))) bf16 Bt[1][CB * RS];
   const int t = find_tile(g, blockIdx.x);
   const int k = blockIdx.x - g.pfx[t];
   const int nb = C / CB;
@@ -1559,8 +1560,8 @@ __global__ __launch_bounds__(256) void k_gram_bf16(const bf16 *act, long long ac
     }
   };
   load_stage(q0);
-  int buf = 0;
-  for (int qs = q0; qs < q1; qs += SP, buf ^= 1) {
+  const int buf = 0;
+  for (int qs = q0; qs < q1; qs += SP) {
 #pragma unroll
     for (int i = 0; i < PT; ++i) {
       const int v = tid + i * 256;
@@ -1594,6 +1595,7 @@ __global__ __launch_bounds__(256) void k_gram_bf16(const bf16 *act, long long ac
         for (int j = 0; j < TB; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
     }
+    __syncthreads();
   }
   float *o = part + g.slot[t] * part_ss + (long long)k * C * C;
 #pragma unroll
