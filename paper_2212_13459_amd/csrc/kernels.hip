@@ -1641,8 +1641,17 @@ __global__ __launch_bounds__(1024) void k_gram_tile_reduce32(const float *part, 
   const int nch = g.pfx[t + 1] - g.pfx[t];
   const long long cc = (long long)C * C;
   const float *q = part + g.slot[t] * part_ss + (long long)(si * 32 + ty) * C + sj * 32 + tx;
+  // in chunk order; the loads of 16 chunks go out together
   double s = 0.0;
-  for (int k = 0; k < nch; ++k) s += (double)q[k * cc];
+  int k = 0;
+  for (; k + 16 <= nch; k += 16) {
+    float v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) v[u] = q[(k + u) * cc];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) s += (double)v[u];
+  }
+  for (; k < nch; ++k) s += (double)q[k * cc];
   sm[ty][tx] = s;   // sum of part[.][si 32 + ty][sj 32 + tx]
   __syncthreads();
   // output (i, j) = (bi 32 + ty, bj 32 + tx) needs part[min(i, j)][max(i, j)]
