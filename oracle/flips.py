@@ -15,9 +15,9 @@ and the change is carried to the image by the same reverse pass as ``loss.backwa
 (conv adjoint, pool routing to the FP64 argmax, ReLU mask), restricted to an aligned
 crop that contains the decision's dependency cone [s q - a, s q + b].
 
-``explain`` subtracts, greedily from the most fragile decision on, the flip effects
-that reduce a candidate gradient's deviation from the FP64 one where they act, and
-returns what remains.  A correct reduced-precision backward leaves only rounding noise.
+``flip_fit`` removes from a reduced-precision gradient's deviation the 0/1 combination
+of these effects that fits it best (least squares, rounded), and returns what remains.
+A correct reduced-precision backward leaves only rounding noise.
 """
 from __future__ import annotations
 
@@ -136,42 +136,66 @@ def flip_effect(net: NetSpec, record, ws, unit, shape):
     return Y0, Y1, X0, X1, _backward_from(net, acts_c, i, dz, ws)
 
 
-def explain(net: NetSpec, x, ws, bs, record, g_ref, g_test, delta=1e-5, floor=1e-6, max_eval=400,
-            passes=3):
-    """Greedy flip correction of g_test - g_ref.  Returns (residual, accepted units).
+def flip_fit(net: NetSpec, x, ws, bs, record, g_ref, g_test, delta=1e-5, floor=1e-6):
+    """Remove from g_test - g_ref the best 0/1 combination of near-tie flip effects.
 
-    Candidates are the decisions with margin/rms < delta, most fragile first.  A flip is
-    accepted when subtracting its effect shrinks the residual on the effect's support by
-    30% or more; passes repeat until one accepts nothing (overlapping flips)."""
+    Candidates are the decisions whose FP64 margin is below ``delta`` times the RMS of
+    their layer (``fragile_units``) and whose dependency crop carries a residual above
+    ``floor`` times max|g_ref| (elsewhere a flip cannot be what the residual shows).  The
+    coefficients c_u of their exact effects e_u (``flip_effect``) are fitted to the
+    residual r by least squares, through the normal equations M c = b with
+    M_uv = <e_u, e_v> and b_u = <e_u, r>, and rounded to 0 or 1 one at a time: the
+    coefficient nearest to 0 or 1 is fixed there, the others are fitted again with the
+    fixed ones subtracted, until every one is fixed (two candidates with the same effect,
+    which plain rounding would split into halves, are then resolved one after the other).
+
+    Returns (r - sum_u c_u e_u, the flipped units, the unrounded first fit)."""
     r = np.asarray(g_test, np.float64) - g_ref
     shape = g_ref.shape[1:]
     acts = [record[("A", i)] for i in range(last_needed(net) + 1)]
-    cands = fragile_units(net, acts, ws, bs, x, delta)
     thresh = floor * float(np.abs(g_ref).max())
-    accepted, cache = [], {}
-    for _ in range(passes):
-        evals, gained = 0, False
-        for u in cands:
-            if u in accepted or evals >= max_eval:
+    units, crops, effects = [], [], []
+    for u in fragile_units(net, acts, ws, bs, x, delta):
+        _, kind, i, c, qy, qx = u
+        span = 2 if kind == "pool" else 1
+        qy0, qx0 = (2 * qy, 2 * qx) if kind == "pool" else (qy, qx)
+        Y0, Y1, X0, X1 = _crop(net, i, qy0, qx0, span, shape)
+        if float(np.abs(r[:, Y0:Y1, X0:X1]).max()) < thresh:
+            continue
+        units.append(u)
+        crops.append((Y0, Y1, X0, X1))
+        effects.append(flip_effect(net, record, ws, u, shape)[4])
+    n = len(units)
+    M = np.zeros((n, n))
+    b = np.zeros(n)
+    for p in range(n):
+        Y0, Y1, X0, X1 = crops[p]
+        b[p] = float(np.sum(effects[p] * r[:, Y0:Y1, X0:X1]))
+        for q in range(p, n):
+            y0, y1 = max(Y0, crops[q][0]), min(Y1, crops[q][1])
+            x0, x1 = max(X0, crops[q][2]), min(X1, crops[q][3])
+            if y0 >= y1 or x0 >= x1:
                 continue
-            _, kind, i, c, qy, qx = u
-            span = 2 if kind == "pool" else 1
-            qy0, qx0 = (2 * qy, 2 * qx) if kind == "pool" else (qy, qx)
-            Y0, Y1, X0, X1 = _crop(net, i, qy0, qx0, span, shape)
-            rc = r[:, Y0:Y1, X0:X1]
-            if float(np.abs(rc).max()) < thresh:
-                continue
-            evals += 1
-            if u not in cache:
-                cache[u] = flip_effect(net, record, ws, u, shape)[4]
-            d = cache[u]
-            sup = np.abs(d) > 1e-12 * max(float(np.abs(d).max()), 1e-300)
-            before = float(np.linalg.norm(rc[sup]))
-            after = float(np.linalg.norm((rc - d)[sup]))
-            if before > 0 and after < 0.7 * before:
-                r[:, Y0:Y1, X0:X1] = rc - d
-                accepted.append(u)
-                gained = True
-        if not gained:
-            break
-    return r, accepted
+            ep = effects[p][:, y0 - Y0:y1 - Y0, x0 - X0:x1 - X0]
+            eq = effects[q][:, y0 - crops[q][0]:y1 - crops[q][0], x0 - crops[q][2]:x1 - crops[q][2]]
+            M[p, q] = M[q, p] = float(np.sum(ep * eq))
+    coef = np.zeros(n)
+    free = list(range(n))
+    first = None
+    while free:
+        fixed = [p for p in range(n) if p not in free]
+        rhs = b[free] - M[np.ix_(free, fixed)] @ coef[fixed]
+        c = np.linalg.lstsq(M[np.ix_(free, free)], rhs, rcond=None)[0]
+        if first is None:
+            first = c.copy()
+        dist = np.minimum(np.abs(c), np.abs(c - 1.0))
+        k = int(np.argmin(dist))
+        coef[free[k]] = 0.0 if abs(c[k]) <= abs(c[k] - 1.0) else 1.0
+        free.pop(k)
+    flipped = []
+    for p in range(n):
+        if coef[p] == 1.0:
+            Y0, Y1, X0, X1 = crops[p]
+            r[:, Y0:Y1, X0:X1] -= effects[p]
+            flipped.append(units[p])
+    return r, flipped, (np.zeros(0) if first is None else first)

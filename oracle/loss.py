@@ -69,7 +69,7 @@ def style_seed(v: np.ndarray, g: np.ndarray, g_t: np.ndarray, w_l: float, n_p: i
     """Gram row of Table 1 on a C x h x w map: (2 w / n_p) V (D + D^T), D = G - G_t."""
     c = v.shape[0]
     d = g - g_t
-    return ((2.0 * w_l / n_p) * ((d + d.T) @ v.reshape(c, -1))).reshape(v.shape)
+    return (((2.0 * w_l / n_p) * (d + d.T)) @ v.reshape(c, -1)).reshape(v.shape)
 
 
 def content_seed(v: np.ndarray, f_ref: np.ndarray, alpha: float) -> np.ndarray:

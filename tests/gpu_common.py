@@ -63,14 +63,14 @@ def oracle_loss(kind, H, W, Hs, Ws, sigma, w_style, alpha, bias=0.0):
 def flip_corrected(kind, H, W, Hs, Ws, sigma, w_style, alpha, g_test, bias=0.0, delta=1e-5):
     """Residual of g_test after removing the exact effects of flipped near-tie decisions
     (decisions whose FP64 margin is below delta x RMS); see oracle.flips."""
-    from oracle.flips import explain
+    from oracle.flips import flip_fit
     terms, g_ref = oracle_loss(kind, H, W, Hs, Ws, sigma, w_style, alpha, bias)
     rec = _records[(kind, H, W, Hs, Ws, sigma, w_style, alpha, bias)]
     k = case(kind, H, W, Hs, Ws, sigma, bias)
     ws = [w.astype(np.float64) for w in k["ws"]]
     bs = [b.astype(np.float64) for b in k["bs"]]
-    r, acc = explain(k["net"], k["x"].astype(np.float64), ws, bs, rec, g_ref, g_test, delta=delta)
-    return float(np.linalg.norm(r) / np.linalg.norm(g_ref)), acc
+    r, flipped, _ = flip_fit(k["net"], k["x"].astype(np.float64), ws, bs, rec, g_ref, g_test, delta=delta)
+    return float(np.linalg.norm(r) / np.linalg.norm(g_ref)), flipped
 
 
 def flat_grams(gs):

@@ -463,24 +463,64 @@ def test_pool_flip_effect_equals_full_backward_difference():
     assert np.abs(full).max() > 0
 
 
-def test_explain_removes_planted_flips_and_keeps_real_errors():
-    from oracle.flips import explain, flip_effect, fragile_units
+def test_flip_fit_removes_planted_flips_and_keeps_real_errors():
+    from oracle.flips import flip_effect, flip_fit, fragile_units
     net, ws, bs, x, rec, acts, seeds, g = _recorded_case()
     units = fragile_units(net, acts, ws, bs, x, 1e-3)
-    pick = [units[0], units[3]]
-    g_test = g.copy()
-    for u in pick:
+    pick, g_test = [], g.copy()
+    for u in units[::3]:                          # three flips whose effect is not zero
         Y0, Y1, X0, X1, d = flip_effect(net, rec, ws, u, g.shape[1:])
-        g_test[:, Y0:Y1, X0:X1] += d
+        if np.abs(d).max() > 1e-6 * np.abs(g).max() and len(pick) < 3:
+            g_test[:, Y0:Y1, X0:X1] += d
+            pick.append(u)
+    assert len(pick) == 3
     rng = np.random.default_rng(0)
     noise = 1e-9 * np.abs(g).max() * rng.standard_normal(g.shape)
-    r, acc = explain(net, x, ws, bs, rec, g, g_test + noise, delta=1e-3)
+    r, flipped, first = flip_fit(net, x, ws, bs, rec, g, g_test + noise, delta=1e-3)
     assert rel(r + g, g) < 1e-7
+    assert sorted(flipped) == sorted(pick)
     # a genuine error (a dropped term) is not explained away
     bad = g_test.copy()
     bad[:, 5:9, 5:9] *= 1.5
-    r2, _ = explain(net, x, ws, bs, rec, g, bad, delta=1e-3)
+    r2, _, _ = flip_fit(net, x, ws, bs, rec, g, bad, delta=1e-3)
     assert rel(r2 + g, g) > 1e-3
+    # nothing to explain: no flips
+    r3, flipped3, _ = flip_fit(net, x, ws, bs, rec, g, g + noise, delta=1e-3)
+    assert flipped3 == [] and np.array_equal(r3, noise + g - g)
+
+
+@pytest.mark.slow
+def test_flip_fit_brings_a_plain_fp32_evaluation_under_1e4():
+    """A plain FP32 evaluation of the definition (FP32 storage and FP32 accumulation, the
+    FP64 oracle's own steps) misses the 1e-4 gradient bar at 200 x 328 on the full net
+    because rounding moves a few near-tie decisions; after the fit it meets it.  This pins
+    that the bar the FP32 GPU tests apply after the fit is reachable by a correct FP32
+    evaluation, and that the fit needs only a handful of flips to get there."""
+    from oracle import bf16ref
+    from oracle.flips import flip_fit
+    from test_oracle_bf16 import _adj_f32, _conv_f32
+    net = vgg19()
+    ws, bs = synth.vgg_weights(net.convs, seed=0)
+    ws = [wi.astype(np.float64) for wi in ws]
+    bs = [bi.astype(np.float64) for bi in bs]
+    c = synth.image(200, 328, 8, 1).astype(np.float64)
+    s = synth.image(176, 208, 8, 2).astype(np.float64)
+    x = synth.image(200, 328, 8, 3).astype(np.float64)
+    g_t = oracle.loss.style_grams(net, s, ws, bs)
+    f_c = oracle.content_features(net, c, ws, bs)
+    rec = {}
+    _, g64 = loss_grad(net, x, ws, bs, g_t, f_c, [0.2] * 5, 0.0, record=rec)
+    q32 = lambda a: np.asarray(a, np.float32).astype(np.float64)   # noqa: E731
+    orig = bf16ref.conv3x3, bf16ref.conv3x3_adjoint
+    bf16ref.conv3x3, bf16ref.conv3x3_adjoint = _conv_f32, _adj_f32
+    try:
+        _, g32 = bf16ref.loss_grad(net, x, ws, bs, g_t, f_c, [0.2] * 5, 0.0, q=q32)
+    finally:
+        bf16ref.conv3x3, bf16ref.conv3x3_adjoint = orig
+    raw = rel(g32, g64)
+    r, flipped, _ = flip_fit(net, x, ws, bs, rec, g64, g32)
+    print(f"fp32 raw {raw:.2e}, after the fit {rel(r + g64, g64):.2e} with {len(flipped)} flips")
+    assert raw > 1e-4 and rel(r + g64, g64) < 1e-5 and len(flipped) <= 10
 
 
 def test_relu_flip_into_all_zero_pool_window():
