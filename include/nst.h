@@ -54,7 +54,9 @@ typedef enum {
   NST_ENOMEM = -4,      /* nst_create could not allocate the packed weights              */
   NST_EHIP = -5,        /* a HIP runtime call failed                                      */
   NST_ECAPACITY = -6,   /* nst_plan: output array too small (needed count is returned)  */
-  NST_EWORKSPACE = -7   /* workspace smaller than nst_workspace_bytes(..., tile_batch=1) */
+  NST_EWORKSPACE = -7,  /* workspace smaller than nst_workspace_bytes(..., tile_batch=1), or
+                           than the every-tile size under NST_RESIDENT                     */
+  NST_ENONFINITE = -8   /* NST_CHECK_FINITE: an input holds a NaN or an infinity          */
 } nst_status;
 
 typedef enum { NST_FP32 = 0, NST_BF16 = 1 } nst_precision;
@@ -63,7 +65,13 @@ enum {
   NST_STEP1 = 1,        /* Algorithm 1 Step 1: global Grams of x (+ energies)            */
   NST_STEP2 = 2,        /* Algorithm 1 Step 2: gradient from given Grams of x            */
   NST_BOTH = 3,
-  NST_STRICT_HALO = 4   /* reject m < nst_min_halo()                                      */
+  NST_STRICT_HALO = 4,  /* reject m < nst_min_halo()                                      */
+  NST_CHECK_FINITE = 8, /* check x, content_feats, target_grams (and grams_x when read),
+                           w_style and alpha for NaN / infinity before any other work;
+                           costs one pass over the inputs and a host wait               */
+  NST_RESIDENT = 16     /* keep every tile's activations from Step 1 to Step 2 of the same
+                           call instead of recomputing them (needs the every-tile
+                           workspace of nst_workspace_bytes; same results, bit for bit)  */
 };
 
 /* A VGG-style feature network: n_conv 3x3 convs (zero padding 1, stride 1), each followed
@@ -112,11 +120,10 @@ int nst_plan(const nst_net_desc *net, int H, int W, int T, int m,
              nst_tile *out, int cap, int *n_tiles);
 
 /* Device workspace needed to process `tile_batch` tiles of the plan at once with the given
- * precision; the run calls use the largest batch that fits in what they are given.  With
- * tile_batch >= the plan's tile count the workspace holds every tile's activations, and
- * nst_loss_grad with NST_STEP1 | NST_STEP2 then runs Step 2's backward on the activations
- * its Step 1 left resident instead of recomputing them (same results, bit for bit).
- * Host only. */
+ * precision; the run calls use the largest batch that fits in what they are given, so
+ * memory is one tile batch's activations plus the Grams (Algorithm 1: Step 2 recomputes
+ * each tile's forward).  tile_batch >= the plan's tile count gives the every-tile size
+ * that NST_RESIDENT needs.  Host only. */
 int nst_workspace_bytes(const nst_net_desc *net, int precision, int H, int W, int T, int m,
                         int tile_batch, size_t *bytes);
 
@@ -147,14 +154,17 @@ int nst_content_feats(nst_ctx *ctx, const float *c, int H, int W, int T, int m, 
  *   content_feats: device float32 content features of the content image at H x W, or NULL
  *                  iff alpha == 0 or the network has no content layer
  *   w_style      : host float64 [n_style], the w_l of Eq. 3
- *   flags        : NST_STEP1 | NST_STEP2 (| NST_STRICT_HALO)
+ *   flags        : NST_STEP1 | NST_STEP2 (| NST_STRICT_HALO | NST_CHECK_FINITE | NST_RESIDENT)
  *   grams_x      : device float64; written by Step 1; read by Step 2 when Step 1 is not
  *                  requested (the autograd backward reuses the forward's Grams)
  *   energy       : host float64 [2 + n_style] = {E, E_content, E_style_l...} or NULL.
  *                  E_content is summed over owned content features of whichever passes ran.
  *   grad         : device float32 3 x H x W, dE/dx, written when NST_STEP2 is set.
- * Memory: one tile batch's activations plus the Grams; nothing whole-image besides the
- * inputs and outputs. */
+ * Memory: one tile batch's activations plus the Grams (every tile's under NST_RESIDENT);
+ * nothing whole-image besides the inputs and outputs.
+ * Errors: NST_EINVAL (NULL pointer, unknown flag, content_feats NULL with alpha != 0 and a
+ * content layer), NST_ESHAPE, NST_EHALO, NST_EWORKSPACE, NST_ENONFINITE (only under
+ * NST_CHECK_FINITE; nothing is written), NST_EHIP. */
 int nst_loss_grad(nst_ctx *ctx, const float *x, int H, int W, const double *target_grams,
                   const float *content_feats, const double *w_style, double alpha, int T,
                   int m, int flags, double *grams_x, double *energy, float *grad, void *ws,

@@ -4,5 +4,5 @@ The compute path is libnst.so (hand-written HIP kernels behind a C ABI, declared
 include/nst.h).  ``nst`` is the thin Python binding; it refuses to run without the
 built library.
 """
-from .nst import (NST_BOTH, NST_STEP1, NST_STEP2, NST_STRICT_HALO, Context, StyleEnergy,  # noqa: F401
-                  min_halo, plan, vgg19_desc, workspace_bytes)
+from .nst import (NST_BOTH, NST_CHECK_FINITE, NST_RESIDENT, NST_STEP1, NST_STEP2, NST_STRICT_HALO,  # noqa: F401
+                  Context, StyleEnergy, min_halo, plan, vgg19_desc, workspace_bytes)

@@ -11,10 +11,10 @@ LIB_PATH = os.path.join(HERE, "libnst.so")
 NST_MAX_CONV = 16
 NST_MAX_STYLE = 8
 NST_FP32, NST_BF16 = 0, 1
-NST_STEP1, NST_STEP2, NST_BOTH, NST_STRICT_HALO = 1, 2, 3, 4
+NST_STEP1, NST_STEP2, NST_BOTH, NST_STRICT_HALO, NST_CHECK_FINITE, NST_RESIDENT = 1, 2, 3, 4, 8, 16
 
 STATUS = {0: "NST_OK", -1: "NST_EINVAL", -2: "NST_ESHAPE", -3: "NST_EHALO", -4: "NST_ENOMEM",
-          -5: "NST_EHIP", -6: "NST_ECAPACITY", -7: "NST_EWORKSPACE"}
+          -5: "NST_EHIP", -6: "NST_ECAPACITY", -7: "NST_EWORKSPACE", -8: "NST_ENONFINITE"}
 
 
 class NetDesc(ctypes.Structure):

@@ -89,6 +89,10 @@ hipError_t launch_stitch_feats(int precision, const void *act, long long act_ss,
                                const Batch &g, float *feats, int feats_w, hipStream_t s);
 hipError_t launch_fill_f64(double *p, size_t n, double v, hipStream_t s);
 hipError_t launch_fill_f32(float *p, size_t n, float v, hipStream_t s);
+hipError_t launch_fill_u32(unsigned *p, size_t n, unsigned v, hipStream_t s);
+// *count += number of NaN / infinite elements of p[0..n)
+hipError_t launch_count_nonfinite_f32(const float *p, size_t n, unsigned *count, hipStream_t s);
+hipError_t launch_count_nonfinite_f64(const double *p, size_t n, unsigned *count, hipStream_t s);
 // g[e] = gacc[e] / n_p for one style layer (the Sec. 3.1 normalization)
 hipError_t launch_gram_normalize(const double *gacc, double *g, size_t n, double n_p,
                                  hipStream_t s);

@@ -1850,6 +1850,43 @@ hipError_t launch_fill_f32(float *p, size_t n, float v, hipStream_t s) {
   return hipGetLastError();
 }
 
+__global__ void k_fill_u32(unsigned *p, size_t n, unsigned v) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+hipError_t launch_fill_u32(unsigned *p, size_t n, unsigned v, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+// Grid-stride count of non-finite elements: a per-thread count, one atomic per wave.
+template <typename T>
+__global__ __launch_bounds__(256) void k_count_nonfinite(const T *p, size_t n, unsigned *count) {
+  unsigned c = 0;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
+    c += isfinite(p[i]) ? 0u : 1u;
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_down(c, o, 64);
+  if ((threadIdx.x & 63) == 0 && c) atomicAdd(count, c);
+}
+
+template <typename T>
+static hipError_t count_nonfinite(const T *p, size_t n, unsigned *count, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const size_t blocks = std::min<size_t>((n + 255) / 256, 2048);
+  hipLaunchKernelGGL(k_count_nonfinite<T>, dim3((unsigned)blocks), dim3(256), 0, s, p, n, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_count_nonfinite_f32(const float *p, size_t n, unsigned *count, hipStream_t s) {
+  return count_nonfinite(p, n, count, s);
+}
+
+hipError_t launch_count_nonfinite_f64(const double *p, size_t n, unsigned *count, hipStream_t s) {
+  return count_nonfinite(p, n, count, s);
+}
+
 __global__ void k_div_f64(const double *in, double *out, size_t n, double d) {
   const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
   if (i < n) out[i] = in[i] / d;

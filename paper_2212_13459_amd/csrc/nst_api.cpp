@@ -4,6 +4,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
@@ -149,7 +150,8 @@ struct Layout {
   int cblocks = 0;
   size_t es = 4;
   // global region
-  size_t g_gacc = 0, g_dt = 0, g_estyle = 0, g_ec = 0, g_energy = 0, g_tilesum = 0;
+  size_t g_gacc = 0, g_dt = 0, g_estyle = 0, g_ec = 0, g_energy = 0, g_tilesum = 0, g_flag = 0;
+  long long total_cc = 0;       // sum over style layers of C_l^2
   long long off_c[NST_MAX_STYLE] = {}, dt_off[NST_MAX_STYLE] = {};
   size_t slots = 0, slot_bytes = 0;
   // per-slot offsets
@@ -225,6 +227,9 @@ void make_layout(const Geom &g, int precision, const std::vector<nst_tile> &tile
   off = al(off + (2 + NST_MAX_STYLE) * 8);
   L.g_tilesum = off;
   off = al(off + (size_t)batch * maxcc * 8);
+  L.g_flag = off;
+  off = al(off + 8);
+  L.total_cc = cc;
   L.slots = off;
   // per slot
   size_t so = 0, dmax = 0;
@@ -352,6 +357,7 @@ const char *nst_strerror(int st) {
     case NST_EHIP: return "HIP runtime error";
     case NST_ECAPACITY: return "output array too small";
     case NST_EWORKSPACE: return "workspace too small";
+    case NST_ENONFINITE: return "non-finite value in an input";
     default: return "unknown status";
   }
 }
@@ -817,10 +823,11 @@ int setup(Runner &R, nst_ctx *ctx, int H, int W, int T, int m, void *ws, size_t 
   make_layout(ctx->g, ctx->prec, R.tiles, 1, 1, L1);
   if ((st = max_window_ok(ctx->g, L1)) != NST_OK) return st;
   if (ws_bytes < L1.total) return NST_EWORKSPACE;
-  // a slot per tile if it fits: Step 2 then reuses Step 1's activations
-  Layout La;
-  make_layout(ctx->g, ctx->prec, R.tiles, balanced_batch(nt), nt, La);
-  if (La.total <= ws_bytes) {
+  if (flags & NST_RESIDENT) {
+    // a slot per tile, asked for explicitly: Step 2 then reuses Step 1's activations
+    Layout La;
+    make_layout(ctx->g, ctx->prec, R.tiles, balanced_batch(nt), nt, La);
+    if (La.total > ws_bytes) return NST_EWORKSPACE;
     R.L = La;
     R.retain = true;
     return NST_OK;
@@ -963,7 +970,9 @@ int nst_loss_grad(nst_ctx *ctx, const float *x, int H, int W, const double *targ
                   int flags, double *grams_x, double *energy, float *grad, void *ws,
                   size_t ws_bytes, void *stream) {
   if (!ctx || !x || !grams_x) return NST_EINVAL;
-  if ((flags & ~(NST_BOTH | NST_STRICT_HALO)) != 0 || (flags & NST_BOTH) == 0) return NST_EINVAL;
+  if ((flags & ~(NST_BOTH | NST_STRICT_HALO | NST_RESIDENT | NST_CHECK_FINITE)) != 0 ||
+      (flags & NST_BOTH) == 0)
+    return NST_EINVAL;
   const Geom &g = ctx->g;
   const bool s1 = flags & NST_STEP1, s2 = flags & NST_STEP2;
   const bool use_c = g.content >= 0 && alpha != 0.0;
@@ -974,6 +983,26 @@ int nst_loss_grad(nst_ctx *ctx, const float *x, int H, int W, const double *targ
   int st = setup(R, ctx, H, W, T, m, ws, ws_bytes, stream, flags);
   if (st != NST_OK) return st;
   const float *fc = use_c ? content_feats : nullptr;
+  if (flags & NST_CHECK_FINITE) {
+    // count non-finite inputs on the device, then wait for the count (a host sync)
+    unsigned *cnt = R.gl<unsigned>(R.L.g_flag);
+    HIPCHK(launch_fill_u32(cnt, 1, 0u, R.s));
+    HIPCHK(launch_count_nonfinite_f32(x, (size_t)3 * H * W, cnt, R.s));
+    if (fc) {
+      const int i = g.content;
+      const size_t n = (size_t)(H / g.stride[i]) * (W / g.stride[i]) * g.cout[i];
+      HIPCHK(launch_count_nonfinite_f32(fc, n, cnt, R.s));
+    }
+    if (g.n_style > 0) HIPCHK(launch_count_nonfinite_f64(target_grams, (size_t)R.L.total_cc, cnt, R.s));
+    if (!s1) HIPCHK(launch_count_nonfinite_f64(grams_x, (size_t)R.L.total_cc, cnt, R.s));
+    unsigned host_cnt = 0;
+    HIPCHK(hipMemcpyAsync(&host_cnt, cnt, sizeof(unsigned), hipMemcpyDeviceToHost, R.s));
+    HIPCHK(hipStreamSynchronize(R.s));
+    if (host_cnt != 0) return NST_ENONFINITE;
+    for (int k = 0; k < g.n_style; ++k)
+      if (!std::isfinite(w_style[k])) return NST_ENONFINITE;
+    if (!std::isfinite(alpha)) return NST_ENONFINITE;
+  }
 
   StyleTermsArgs sa;
   std::memset(&sa, 0, sizeof(sa));

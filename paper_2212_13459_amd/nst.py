@@ -11,8 +11,8 @@ from ctypes import POINTER, byref, c_double, c_float, c_int, c_size_t, c_void_p
 import numpy as np
 import torch
 
-from ._lib import (NST_BF16, NST_BOTH, NST_FP32, NST_STEP1, NST_STEP2, NST_STRICT_HALO, NetDesc, Tile,
-                   check, lib)
+from ._lib import (NST_BF16, NST_BOTH, NST_CHECK_FINITE, NST_FP32, NST_RESIDENT, NST_STEP1, NST_STEP2,
+                   NST_STRICT_HALO, NetDesc, Tile, check, lib)
 
 PRECISIONS = {"fp32": NST_FP32, "bf16": NST_BF16}
 
@@ -71,7 +71,10 @@ class Context:
 
     def __init__(self, weights, biases=None, precision: str = "fp32", desc: NetDesc | None = None,
                  tiny: bool = False, with_content: bool = True, ws_limit: int = 96 << 30,
-                 tile_batch: int = 32, retain: bool = True):
+                 tile_batch: int = 32, resident: bool = False):
+        """resident: keep every tile's activations from Step 1 to Step 2 of a loss_grad call
+        (NST_RESIDENT, a workspace for every tile) instead of recomputing them per tile
+        batch as Algorithm 1 does."""
         self.desc = desc if desc is not None else vgg19_desc(tiny, with_content)
         self.convs, self.style, self.content = desc_info(self.desc)
         self.precision = precision
@@ -88,7 +91,7 @@ class Context:
         self._h = h
         self.ws_limit = ws_limit
         self.tile_batch = tile_batch
-        self.retain = retain
+        self.resident = resident
         self._ws = {}
         strides, s = [], 1
         for i in range(n):
@@ -133,19 +136,19 @@ class Context:
         return out
 
     def workspace(self, H, W, T, m):
-        """Device workspace: a slot per tile when retain is set and that fits in ws_limit
-        (Step 2 then reuses Step 1's activations), else the largest tile batch that fits
-        (at most tile_batch, below the tile count)."""
+        """Device workspace: the largest tile batch (at most tile_batch) that fits in
+        ws_limit, or a slot for every tile when the context is resident."""
         key = (H, W, T, m)
         if key not in self._ws:
             nt = len(plan(self.desc, H, W, T, m))
-            nbytes = workspace_bytes(self.desc, self.precision, H, W, T, m, nt)
-            if not self.retain or nbytes > self.ws_limit:
-                b = min(self.tile_batch, nt - 1) if nt > 1 else 1
+            b = nt if self.resident else max(1, min(self.tile_batch, nt))
+            nbytes = workspace_bytes(self.desc, self.precision, H, W, T, m, b)
+            if self.resident and nbytes > self.ws_limit:
+                raise MemoryError(f"resident workspace {nbytes} B exceeds ws_limit {self.ws_limit} B")
+            while b > 1 and nbytes > self.ws_limit:
+                b -= 1
                 nbytes = workspace_bytes(self.desc, self.precision, H, W, T, m, b)
-                while b > 1 and nbytes > self.ws_limit:
-                    b -= 1
-                    nbytes = workspace_bytes(self.desc, self.precision, H, W, T, m, b)
+            self._ws = {}
             self._ws = {key: torch.empty(nbytes, dtype=torch.uint8, device=self.device)}
         return self._ws[key]
 
@@ -199,6 +202,8 @@ class Context:
         wst = (c_double * max(ns, 1))(*[float(v) for v in w_style])
         en = (c_double * (2 + ns))()
         cf = _ptr(content_feats) if content_feats is not None else c_void_p()
+        if self.resident:
+            flags |= NST_RESIDENT
         check("nst_loss_grad", lib().nst_loss_grad(
             self._h, _ptr(x), H, W, _ptr(target_grams), cf, wst, float(alpha), T, m, flags, _ptr(grams_x),
             en if want_energy else None, _ptr(grad) if grad is not None else c_void_p(), _ptr(ws), ws.numel(),
@@ -228,4 +233,4 @@ class StyleEnergy(torch.autograd.Function):
 
 
 __all__ = ["Context", "StyleEnergy", "vgg19_desc", "min_halo", "plan", "workspace_bytes", "NST_STEP1",
-           "NST_STEP2", "NST_BOTH", "NST_STRICT_HALO"]
+           "NST_STEP2", "NST_BOTH", "NST_STRICT_HALO", "NST_CHECK_FINITE", "NST_RESIDENT"]

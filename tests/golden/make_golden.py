@@ -1,14 +1,24 @@
 """Write FP64 oracle reference values for the full-size workloads (calls oracle/ only).
 
-    python tests/golden/make_golden.py [C2|C3|C4 ...]
+    python tests/golden/make_golden.py [C2|C3|C3p1|C4 ...]
 
 For each configuration the oracle evaluates the tiled two-pass loss (Algorithm 1, its
-own planner) on the seeded synthetic inputs and stores, as JSON: the energy terms,
-per-layer Gram summaries of x and of the style image (trace, Frobenius norm, the
-diagonal and the first 8x8 block), content-feature sums, and dE/dx at sampled pixels
-(Step 2 run only on the tiles that hold the samples).  A tiled oracle result equals the
-whole-image one to ~1e-13 (pinned in tests/test_oracle.py), so these are whole-image
-reference values.
+own planner) on the seeded synthetic inputs and stores, as JSON:
+
+* the energy terms;
+* per style layer, for x and for the style image: the Gram summaries (trace, Frobenius
+  norm, diagonal, first 8x8 block) and the probe products G P with P a seeded C x 16
+  standard-normal matrix (seed 5, drawn layer after layer), which any wrong block of G
+  changes; the full Grams of x for layers with C <= 128;
+* content features: sum, sum of squares and the values at 384 seeded (c, y, x);
+* dE/dx at 512 pixels of two tiles (the one holding the image centre and the last,
+  ragged one), a third of them within 6 px of a block edge (Step 2 run only on those
+  tiles), and for C2 central finite differences at the first 64 of them.
+
+A tiled oracle result equals the whole-image one to ~1e-13 (pinned in
+tests/test_oracle.py), so these are whole-image reference values.  C3p1 is the
+3024 x 4032 level of the content pyramid (x and c box-downsampled by 2 from their
+6048 x 8064 versions; the style image keeps its size).
 """
 import json
 import os
@@ -30,9 +40,9 @@ from oracle.net import receptive_fields  # noqa: E402
 from oracle.tiled import step1, step2, tiled_content_features  # noqa: E402
 
 CONFIGS = {
-    # name: (H, W, Hs, Ws, sigma, T, m, samples per tile, tiles sampled)
     "C2": dict(H=2048, W=2048, Hs=1024, Ws=1280, sigma=8.0, T=512, m=155),
     "C3": dict(H=6048, W=8064, Hs=4226, Ws=5319, sigma=16.0, T=1024, m=155),
+    "C3p1": dict(H=3024, W=4032, Hs=4226, Ws=5319, sigma=16.0, T=1024, m=155, down=1),
     "C4": dict(H=3024, W=4032, Hs=2000, Ws=2000, sigma=16.0, T=1000, m=155),
 }
 W_STYLE = [0.2] * 5
@@ -44,8 +54,15 @@ def summarize(g):
             "diag": [float(v) for v in np.diag(g)], "block8": [[float(v) for v in r] for r in g[:8, :8]]}
 
 
-def sample_pixels(H, W, T, m, seed=4, per_tile=32):
-    """Pixels in two tiles: the one holding the image centre and the last (ragged) one."""
+def probes(sizes, seed=5):
+    rng = np.random.default_rng(seed)
+    return [rng.standard_normal((c, 16)) for c in sizes]
+
+
+def sample_pixels(H, W, T, m, seed=4, per_tile=256, edge=6):
+    """Pixels in two tiles: the one holding the image centre and the last (ragged) one;
+    per tile two thirds uniform over the block and one third within ``edge`` px of one
+    of its four edges."""
     net = oracle.vgg19()
     plan = make_plan(H, W, T, m, net.strides(), net.align())
     centre = next(k for k, t in enumerate(plan) if t.by0 <= H // 2 < t.by1 and t.bx0 <= W // 2 < t.bx1)
@@ -54,8 +71,20 @@ def sample_pixels(H, W, T, m, seed=4, per_tile=32):
     out = []
     for k in picks:
         t = plan[k]
-        for _ in range(per_tile):
-            out.append((int(rng.integers(3)), int(rng.integers(t.by0, t.by1)), int(rng.integers(t.bx0, t.bx1))))
+        for j in range(per_tile):
+            ch = int(rng.integers(3))
+            y, x = int(rng.integers(t.by0, t.by1)), int(rng.integers(t.bx0, t.bx1))
+            if 3 * j >= 2 * per_tile:
+                side, d = int(rng.integers(4)), int(rng.integers(edge))
+                if side == 0:
+                    y = t.by0 + d
+                elif side == 1:
+                    y = t.by1 - 1 - d
+                elif side == 2:
+                    x = t.bx0 + d
+                else:
+                    x = t.bx1 - 1 - d
+            out.append((ch, y, x))
     return picks, out
 
 
@@ -111,17 +140,28 @@ def local_fd(net, x, w64, b64, g_x, g_t, f_c, px, h=1e-3):
     return out
 
 
+def images(cfg):
+    H, W, Hs, Ws, sigma = (cfg[k] for k in ("H", "W", "Hs", "Ws", "sigma"))
+    down = cfg.get("down", 0)
+    xs = []
+    for seed in (synth.SEED_X, synth.SEED_CONTENT):
+        a = synth.image(H << down, W << down, sigma, seed)
+        for _ in range(down):
+            a = synth.box_down2(a)
+        xs.append(a.astype(np.float64))
+    s = synth.image(Hs, Ws, sigma, synth.SEED_STYLE).astype(np.float64)
+    return xs[0], xs[1], s
+
+
 def run(name):
     cfg = CONFIGS[name]
-    H, W, Hs, Ws, sigma, T, m = (cfg[k] for k in ("H", "W", "Hs", "Ws", "sigma", "T", "m"))
+    H, W, T, m = (cfg[k] for k in ("H", "W", "T", "m"))
     t0 = time.time()
     net = oracle.vgg19()
     ws, bs = synth.vgg_weights(net.convs, synth.SEED_WEIGHTS)
     w64 = [w.astype(np.float64) for w in ws]
     b64 = [b.astype(np.float64) for b in bs]
-    x = synth.image(H, W, sigma, synth.SEED_X).astype(np.float64)
-    c = synth.image(H, W, sigma, synth.SEED_CONTENT).astype(np.float64)
-    s = synth.image(Hs, Ws, sigma, synth.SEED_STYLE).astype(np.float64)
+    x, c, s = images(cfg)
     print(f"[{name}] inputs {time.time() - t0:.0f}s", flush=True)
     g_t, _ = step1(net, s, w64, b64, T, m)
     print(f"[{name}] style grams {time.time() - t0:.0f}s", flush=True)
@@ -133,14 +173,24 @@ def run(name):
     picks, px = sample_pixels(H, W, T, m)
     grad = step2(net, x, w64, g_x, g_t, f_c, W_STYLE, ALPHA, T, m, b64, only=set(picks))
     print(f"[{name}] step 2 on tiles {picks} {time.time() - t0:.0f}s", flush=True)
-    fd = local_fd(net, x, w64, b64, g_x, g_t, f_c, px) if name == "C2" else None
+    fd = local_fd(net, x, w64, b64, g_x, g_t, f_c, px[:64]) if name == "C2" else None
     print(f"[{name}] finite differences {time.time() - t0:.0f}s", flush=True)
+    P = probes([g.shape[0] for g in g_x])
+    rng = np.random.default_rng(6)
+    cs, ch, cw = f_c.shape
+    fsmp = [(int(rng.integers(cs)), int(rng.integers(ch)), int(rng.integers(cw))) for _ in range(384)]
     out = {
         "config": cfg, "w_style": W_STYLE, "alpha": ALPHA,
         "E": terms["E"], "E_content": terms["E_content"], "E_style": terms["E_style"],
         "grams_x": [summarize(g) for g in g_x], "grams_style": [summarize(g) for g in g_t],
-        "content_feats": {"sum": float(f_c.sum()), "sumsq": float((f_c ** 2).sum())},
-        "grad_samples": [[ch, y, xx, float(grad[ch, y, xx])] for ch, y, xx in px],
+        "probe_seed": 5,
+        "grams_x_probe": [(g @ p).tolist() for g, p in zip(g_x, P)],
+        "grams_style_probe": [(g @ p).tolist() for g, p in zip(g_t, P)],
+        "grams_x_full": [g.tolist() if g.shape[0] <= 128 else None for g in g_x],
+        "content_feats": {"sum": float(f_c.sum()), "sumsq": float((f_c ** 2).sum()),
+                          "samples": [[a, b, d, float(f_c[a, b, d])] for a, b, d in fsmp]},
+        "grad_tiles": picks,
+        "grad_samples": [[ch_, y, xx, float(grad[ch_, y, xx])] for ch_, y, xx in px],
         "fd_h": 1e-3, "fd_samples": fd,
         "seconds": time.time() - t0,
     }
@@ -150,5 +200,5 @@ def run(name):
 
 
 if __name__ == "__main__":
-    for name in sys.argv[1:] or ["C2", "C4", "C3"]:
+    for name in sys.argv[1:] or ["C2", "C4", "C3p1", "C3"]:
         run(name)

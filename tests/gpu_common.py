@@ -6,7 +6,9 @@ import torch
 
 import oracle
 import synth
+from oracle import bf16ref
 from oracle.loss import content_features, loss_grad, style_grams
+from oracle.ops import conv3x3, maxpool2, relu
 
 
 def rel(a, b):
@@ -60,6 +62,18 @@ def oracle_loss(kind, H, W, Hs, Ws, sigma, w_style, alpha, bias=0.0):
     return terms, grad
 
 
+@functools.lru_cache(maxsize=None)
+def bf16ref_loss(kind, H, W, Hs, Ws, sigma, w_style, alpha, bias=0.0):
+    """The BF16-storage reference (oracle/bf16ref.py) on the oracle's FP64 targets."""
+    from oracle import bf16ref
+    k = case(kind, H, W, Hs, Ws, sigma, bias)
+    ws = [w.astype(np.float64) for w in k["ws"]]
+    bs = [b.astype(np.float64) for b in k["bs"]]
+    g_t, f_c = oracle_targets(kind, H, W, Hs, Ws, sigma, bias)
+    f_c32 = f_c.astype(np.float32).astype(np.float64)
+    return bf16ref.loss_grad(k["net"], k["x"].astype(np.float64), ws, bs, g_t, f_c32, list(w_style), alpha)
+
+
 def flip_corrected(kind, H, W, Hs, Ws, sigma, w_style, alpha, g_test, bias=0.0, delta=1e-5):
     """Residual of g_test after removing the exact effects of flipped near-tie decisions
     (decisions whose FP64 margin is below delta x RMS); see oracle.flips."""
@@ -79,3 +93,78 @@ def flat_grams(gs):
 
 def fc_hwc(f_c):
     return np.ascontiguousarray(np.transpose(f_c, (1, 2, 0)))
+
+
+# ------------------------------------------ stage checks on the GPU's own inputs ----
+
+def quant(prec):
+    return bf16ref.round_bf16 if prec == "bf16" else bf16ref.identity
+
+
+def gpu_acts(nst, x_d, T, m, top):
+    """The GPU's stored post-ReLU features of conv 0..top, whole image, C x h x w FP64."""
+    out = []
+    for i in range(top + 1):
+        f = nst.layer_feats(x_d, T, m, i)
+        out.append(np.ascontiguousarray(f.permute(2, 0, 1).double().cpu().numpy()))
+    return out
+
+
+def layer_input(net, acts, i, x0):
+    if i == 0:
+        return x0
+    return maxpool2(acts[i - 1]) if (i - 1) in net.pool_after else acts[i - 1]
+
+
+def bf16_units_apart(a, b):
+    """Distance in BF16 units of non-negative BF16-exact values (bit patterns are monotone)."""
+    ia = (a.astype(np.float32).view(np.int32) >> 16).astype(np.int64)
+    ib = (b.astype(np.float32).view(np.int32) >> 16).astype(np.int64)
+    return np.abs(ia - ib)
+
+
+def check_forward(net, acts, ws, bs, x, prec, label):
+    q = quant(prec)
+    x0 = q(np.asarray(x, np.float64))
+    worst = []
+    for i in range(len(acts)):
+        ref = q(relu(conv3x3(layer_input(net, acts, i, x0), q(ws[i]), bs[i])))
+        a = acts[i]
+        assert a.shape == ref.shape, (i, a.shape, ref.shape)
+        rms = float(np.sqrt(np.mean(ref * ref))) or 1.0
+        if prec == "fp32":
+            e = float(np.abs(a - ref).max()) / rms
+            f = float(np.linalg.norm(a - ref) / max(np.linalg.norm(ref), 1e-300))
+            print(f"  [{label} fwd fp32] conv {i}: rel {f:.2e}, max|A-A*|/rms {e:.2e}", flush=True)
+            worst.append(e)
+            assert f <= 1e-5 and e <= 1e-4, (i, f, e)
+        else:
+            units = bf16_units_apart(a, ref)
+            # a ReLU input within accumulation rounding of 0 may give a tiny positive value
+            # on one side and 0 on the other: adjacent in value though not in BF16 units
+            near0 = np.abs(a - ref) <= 1e-5 * rms
+            far = int(np.count_nonzero((units > 1) & ~near0))
+            frac = float(np.count_nonzero(a != ref)) / a.size
+            print(f"  [{label} fwd bf16] conv {i}: {frac:.2e} of elements one BF16 unit off, "
+                  f"{far} further", flush=True)
+            worst.append(frac)
+            assert far == 0, (i, far)
+            assert frac <= 1e-3, (i, frac)
+    return worst
+
+
+def seeds_on(net, acts, raw_c, grams_x, g_t, f_c, w_style, alpha, prec, n_ps=None):
+    """Table 1 seeds on the given activations: style (2 w / n_p)(D + D^T) stored in the
+    compute precision, content 2 alpha (V - F_c) from the unrounded content value.
+    n_ps: whole-image feature counts per style layer (default: those of ``acts``)."""
+    q = quant(prec)
+    seeds = {}
+    for k, i in enumerate(net.style):
+        c, h, w = acts[i].shape
+        n_p = h * w if n_ps is None else n_ps[k]
+        d = grams_x[k] - g_t[k]
+        dt = q((2.0 * w_style[k] / n_p) * (d + d.T))
+        seeds[i] = (dt @ acts[i].reshape(c, -1)).reshape(acts[i].shape)
+    if net.content is not None and alpha != 0.0:
+        seeds[net.content] = seeds.get(net.content, 0.0) + 2.0 * alpha * (raw_c - f_c)
+    return seeds

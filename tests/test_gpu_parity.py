@@ -13,17 +13,27 @@ the bar, the test removes the exact FP64 effects of flipping decisions whose mar
 below 1e-5 x RMS (oracle.flips, pinned on the CPU) and applies the bar to what
 remains; the raw error and the flips used are printed.
 
-BF16 errors are stated by the test output and held to a loose bound that catches
-indexing bugs, not rounding: BF16 activations carry ~4e-3 relative rounding, which
-flips far more near-tie decisions, so the BF16 gradient differs from the FP64 one by
-tens of percent in norm while Grams and energies stay within ~1e-2.
+BF16 end-to-end results are compared with two references on the same inputs:
+
+* the FP64 oracle: the error is stated; it is the error of BF16 storage itself, which
+  the BF16-storage reference (oracle/bf16ref.py, FP64 arithmetic rounded to BF16 where a
+  BF16 evaluation stores a value) shows on its own.  Activation rounding (~2e-3) flips
+  max-pool and ReLU decisions all over the image, which moves the image gradient by
+  ~0.2-0.4 in norm.  The bar is that the GPU is no further from FP64 than that
+  reference is (x 1.25 + 0.02); Grams and energies within 2e-2 / 3e-2;
+* the BF16-storage reference: Grams, energies and gradient within the spread that FP32
+  accumulation alone produces between two BF16-storage evaluations
+  (tests/test_oracle_bf16.py: Grams 2e-3, energies 5e-4, gradient 0.2 on the full net).
+
+Each kernel is held to tight bars on identical inputs in tests/test_gpu_layers.py.
 """
 
 import numpy as np
 import pytest
 import torch
 
-from gpu_common import case, cuda, fc_hwc, flat_grams, flip_corrected, oracle_loss, oracle_targets, rel, to_np
+from gpu_common import (bf16ref_loss, case, cuda, fc_hwc, flat_grams, flip_corrected, oracle_loss, oracle_targets,
+                        rel, to_np)
 
 pytestmark = pytest.mark.gpu
 
@@ -82,6 +92,17 @@ def compare(spec, prec, T, m, w_style, alpha, gram_tol, grad_tol, e_tol, bias=0.
             eerr.append(abs(a - b) / abs(b))
     print(f"[{label} {prec} {spec} T={T} m={m} alpha={alpha} w={w_style}] gram rel {['%.2e' % e for e in gerr]}"
           f" grad rel {derr:.2e} energy rel {['%.2e' % e for e in eerr]}", flush=True)
+    if prec == "bf16":
+        bterms, bgrad = bf16ref_loss(kind, H, W, Hs, Ws, sigma, tuple(w_style), alpha, bias)
+        ref_err = rel(bgrad, ograd)
+        bg = [rel(to_np(g), go) for g, go in zip(grams, bterms["grams"])]
+        be = [abs(energy[0] - bterms["E"]) / abs(bterms["E"])]
+        bd = rel(to_np(grad), bgrad)
+        print(f"    BF16-storage reference vs FP64 grad {ref_err:.2e}; GPU vs that reference: gram "
+              f"{['%.1e' % e for e in bg]} energy {be[0]:.1e} grad {bd:.2e}", flush=True)
+        gram_spread, e_spread, grad_spread = (1e-4, 2e-4, 3e-2) if kind == "tiny" else (2e-3, 5e-4, 0.2)
+        assert max(bg) <= gram_spread and be[0] <= e_spread and bd <= grad_spread, (bg, be, bd)
+        grad_tol = 1.25 * ref_err + 0.02
     assert max(gerr) <= gram_tol, gerr
     assert max(eerr) <= e_tol, eerr
     if derr > grad_tol and prec == "fp32":
@@ -109,16 +130,16 @@ def test_full_ragged_tiles_fp32(alpha, w):
     compare(RAGGED, "fp32", 96, 155, w, alpha, 1e-5, 1e-4, 1e-5, label="ragged")
 
 
-# ------------------------------------------------------------------ BF16 stated ----
+# ------------------------------------------------------------------------ BF16 ----
 
 @pytest.mark.parametrize("alpha,w", [(1.0, W3), (0.0, W3)])
-def test_tiny_bf16_stated(alpha, w):
-    compare(TINY, "bf16", 64, 23, w, alpha, 2e-2, 0.6, 3e-2, label="C0")
+def test_tiny_bf16(alpha, w):
+    compare(TINY, "bf16", 64, 23, w, alpha, 2e-2, None, 3e-2, label="C0")
 
 
 @pytest.mark.parametrize("alpha,w", [(1.0, W5), (0.0, W5)])
-def test_full_ragged_bf16_stated(alpha, w):
-    compare(RAGGED, "bf16", 96, 155, w, alpha, 2e-2, 0.6, 3e-2, label="ragged")
+def test_full_ragged_bf16(alpha, w):
+    compare(RAGGED, "bf16", 96, 155, w, alpha, 2e-2, None, 3e-2, label="ragged")
 
 
 # --------------------------------------------------------- targets and features ----
@@ -205,13 +226,13 @@ def test_deterministic(prec):
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 def test_step2_reuse_equals_recompute(prec):
-    """A workspace with a slot per tile (Step 2 reuses the activations Step 1 left
-    resident) and one with two tile slots (Step 2 recomputes them batch by batch, as in
-    Algorithm 1) give bit-identical energies, Grams of x and gradients (12 tiles)."""
+    """Step 2 recomputing each tile batch's forward (Algorithm 1, the default, here with
+    two tile slots) and Step 2 on the activations Step 1 left resident (NST_RESIDENT, a
+    slot per tile) give bit-identical energies, Grams of x and gradients (12 tiles)."""
     from paper_2212_13459_amd import Context, plan
     k = case(*RAGGED)
-    resident = ctx("full", prec)
-    recompute = Context(k["ws"], k["bs"], prec, tile_batch=2, retain=False)
+    recompute = Context(k["ws"], k["bs"], prec, tile_batch=2)
+    resident = Context(k["ws"], k["bs"], prec, resident=True)
     assert len(plan(resident.desc, k["H"], k["W"], 96, 155)) == 12
     g_t, f_c = oracle_targets(*RAGGED)
     gt_d = cuda(flat_grams(g_t), torch.float64)
@@ -223,6 +244,64 @@ def test_step2_reuse_equals_recompute(prec):
     torch.cuda.synchronize()
     assert resident.workspace(k["H"], k["W"], 96, 155).numel() > recompute.workspace(k["H"], k["W"], 96, 155).numel()
     assert e1 == e2 and torch.equal(g1, g2) and torch.equal(d1, d2)
+
+
+def test_resident_needs_the_every_tile_workspace():
+    """NST_RESIDENT with a workspace that holds only a tile batch is refused."""
+    import ctypes
+    from ctypes import c_void_p
+
+    from paper_2212_13459_amd import NST_RESIDENT, workspace_bytes
+    from paper_2212_13459_amd._lib import lib
+    from paper_2212_13459_amd.nst import _ptr
+    k = case(*RAGGED)
+    nst = ctx("full", "fp32")
+    g_t, f_c = oracle_targets(*RAGGED)
+    gt_d = cuda(flat_grams(g_t), torch.float64)
+    fc_d = cuda(fc_hwc(f_c))
+    x = cuda(k["x"])
+    nb = workspace_bytes(nst.desc, "fp32", 200, 328, 96, 155, 2)
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    w = (ctypes.c_double * 5)(*W5)
+    gx, grad = torch.empty_like(gt_d), torch.empty_like(x)
+    st = lib().nst_loss_grad(nst._h, _ptr(x), 200, 328, _ptr(gt_d), _ptr(fc_d), w, 1.0, 96, 155, 3 | NST_RESIDENT,
+                             _ptr(gx), None, _ptr(grad), _ptr(ws), nb, c_void_p())
+    assert st == -7
+    st = lib().nst_loss_grad(nst._h, _ptr(x), 200, 328, _ptr(gt_d), _ptr(fc_d), w, 1.0, 96, 155, 3,
+                             _ptr(gx), None, _ptr(grad), _ptr(ws), nb, c_void_p())
+    assert st == 0
+
+
+@pytest.mark.parametrize("where", ["x", "content", "grams", "weight"])
+def test_check_finite(where):
+    """NST_CHECK_FINITE refuses a NaN or infinity in any input with NST_ENONFINITE and
+    leaves the outputs untouched; without the flag the same finite call succeeds."""
+    from paper_2212_13459_amd import NST_CHECK_FINITE
+    from paper_2212_13459_amd._lib import NstError
+    k = case(*RAGGED)
+    nst = ctx("full", "fp32")
+    g_t, f_c = oracle_targets(*RAGGED)
+    gt_d = cuda(flat_grams(g_t), torch.float64)
+    fc_d = cuda(fc_hwc(f_c))
+    x = cuda(k["x"])
+    e, _, _ = nst.loss_grad(x, gt_d, fc_d, W5, 1.0, 96, 155, flags=3 | NST_CHECK_FINITE)
+    assert np.isfinite(e[0])
+    w = list(W5)
+    if where == "x":
+        x[1, 7, 11] = float("nan")
+    elif where == "content":
+        fc_d[3, 2, 5] = float("inf")
+    elif where == "grams":
+        gt_d[100] = float("-inf")
+    else:
+        w[2] = float("nan")
+    gx = torch.full_like(gt_d, 7.0)
+    grad = torch.full_like(x, 7.0)
+    with pytest.raises(NstError) as ei:
+        nst.loss_grad(x, gt_d, fc_d, w, 1.0, 96, 155, flags=3 | NST_CHECK_FINITE, grams_x=gx, grad=grad)
+    assert ei.value.status == -8
+    torch.cuda.synchronize()
+    assert bool((gx == 7.0).all()) and bool((grad == 7.0).all())
 
 
 def test_zero_energy_when_x_c_s_coincide_fp32():
