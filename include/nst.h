@@ -139,6 +139,14 @@ void nst_destroy(nst_ctx *ctx);
 int nst_style_grams(nst_ctx *ctx, const float *s, int H, int W, int T, int m, double *grams,
                     void *ws, size_t ws_bytes, void *stream);
 
+/* Style statistics of image s for the augmented style loss (Sec. 3.2, Eq. 5; Algorithm 1
+ * Require): the Grams as nst_style_grams and, when means != NULL, the spatial mean of
+ * each channel of each style layer, mean(V_l(s)), accumulated block by block like the
+ * Grams (FP32 per 2048-pixel chunk, FP64 across chunks and blocks, fixed order).
+ * means: device float64, sum_l C_l values, style layers in network order. */
+int nst_style_stats(nst_ctx *ctx, const float *s, int H, int W, int T, int m, double *grams,
+                    double *means, void *ws, size_t ws_bytes, void *stream);
+
 /* Post-ReLU features of conv `conv` for image img, computed block by block and written to
  * the whole-image map feats (device float32, h x w x C_conv).  With conv == content_conv
  * this is the content-feature input of Algorithm 1. */
@@ -169,6 +177,28 @@ int nst_loss_grad(nst_ctx *ctx, const float *x, int H, int W, const double *targ
                   const float *content_feats, const double *w_style, double alpha, int T,
                   int m, int flags, double *grams_x, double *energy, float *grad, void *ws,
                   size_t ws_bytes, void *stream);
+
+/* The augmented style loss (Sec. 3.2, Eq. 5): each style layer's term becomes
+ *   w_l ||G_l(x) - G_l(s)||_F^2 + w'_l ||mean_l(x) - mean_l(s)||^2 + w''_l ||std_l(x) - std_l(s)||^2
+ * with per-channel spatial mean and standard deviation, std = (diag(G) - mean^2)^(1/2)
+ * (Algorithm 1 Step 1; a negative radicand counts as 0).  Feature gradients: Table 1 rows
+ * 3 and 4; on a channel whose std is 0 the std row is taken as 0. */
+typedef struct {
+  const double *w_mean;         /* host [n_style]: w'_l                                        */
+  const double *w_std;          /* host [n_style]: w''_l                                       */
+  const double *target_means;   /* device float64 [sum_l C_l]: mean_l(s) (nst_style_stats); the
+                                   target std comes from it and the target Gram's diagonal    */
+  double *means_x;              /* device float64 [sum_l C_l]: mean_l(x), written by Step 1,
+                                   read by a call that runs Step 2 alone                       */
+} nst_mean_std;
+
+/* nst_loss_grad with the augmented style loss; ms == NULL is nst_loss_grad itself.
+ * energy[2 + l] is layer l's whole augmented term.  Errors as nst_loss_grad, and
+ * NST_EINVAL when a pointer of *ms is NULL. */
+int nst_loss_grad_ms(nst_ctx *ctx, const float *x, int H, int W, const double *target_grams,
+                     const float *content_feats, const double *w_style, double alpha,
+                     const nst_mean_std *ms, int T, int m, int flags, double *grams_x,
+                     double *energy, float *grad, void *ws, size_t ws_bytes, void *stream);
 
 /* ---- Profiling (instrumentation of the entry points above; not part of the method) ----
  * While enabled, every kernel the run calls enqueue is bracketed by two HIP events on the

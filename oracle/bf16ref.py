@@ -7,7 +7,10 @@ each point where a BF16 evaluation stores it, namely
 * the operands of the convolutions: the network weights and the input image;
 * every post-ReLU activation A_i.  The Gram matrices, the max pooling and the ReLU masks
   of the backward pass read these stored values;
-* the residual operand (2 w_l / n_p)(D_l + D_l^T) of each style layer (Table 1, Gram row);
+* the residual operand (2 w_l / n_p)(D_l + D_l^T) of each style layer (Table 1, Gram row),
+  with the augmented loss (Eq. 5) plus diag(r), r = (2 w'' / n_p)(std - std_ref) / std, the
+  part of the std row that multiplies V; the per-channel rest of the mean and std rows,
+  (2 w' / n_p)(mean - mean_ref) - r mean, is added unrounded;
 * every stored adjoint: the masked dE/dZ_i of each conv, and the gradient that reaches
   a max pool's output before it is routed back.
 
@@ -25,7 +28,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .loss import energy_terms, gram, last_needed
+from .loss import channel_mean, energy_terms, gram, last_needed, std_from_stats
 from .net import NetSpec
 from .ops import conv3x3, conv3x3_adjoint, maxpool2, maxpool2_backward, relu
 
@@ -77,27 +80,47 @@ def backward(net: NetSpec, acts, seeds: dict, ws, q=round_bf16) -> np.ndarray:
     return g
 
 
-def loss_grad(net: NetSpec, x, ws, bs, grams_t, f_c, w_style, alpha, q=round_bf16, want_grad=True):
-    """Energy terms (with the Grams of x under "grams") and dE/dx, BF16 storage."""
+def ms_operands(g, g_t, mean, mean_t, w1, w2, n_p):
+    """(r, b) of the mean and std rows of Table 1 written as V diag(r) + b:
+    r = (2 w'' / n_p)(std - std_ref) / std (0 where std = 0), b = (2 w' / n_p)(mean - mean_ref) - r mean."""
+    std, std_t = std_from_stats(g, mean), std_from_stats(g_t, mean_t)
+    r = np.where(std > 0.0, (2.0 * w2 / n_p) * (std - std_t) / np.where(std > 0.0, std, 1.0), 0.0)
+    return r, (2.0 * w1 / n_p) * (mean - mean_t) - r * mean
+
+
+def loss_grad(net: NetSpec, x, ws, bs, grams_t, f_c, w_style, alpha, q=round_bf16, want_grad=True, ms=None):
+    """Energy terms (with the Grams of x under "grams", the channel means under "means")
+    and dE/dx, BF16 storage.  ``ms``: the mean/std terms of Eq. 5 (oracle.loss.MeanStd)."""
     acts, raw = forward(net, x, ws, bs, q)
-    grams_x, n_ps = [], []
+    grams_x, n_ps, means_x = [], [], []
     for i in net.style:
         n_p = acts[i].shape[1] * acts[i].shape[2]
         n_ps.append(n_p)
         grams_x.append(gram(acts[i], n_p))
+        means_x.append(channel_mean(acts[i], n_p))
     e_c = 0.0
     if net.content is not None and alpha != 0.0:
         e_c = float(alpha * np.sum((raw[net.content] - f_c) ** 2))
-    terms = energy_terms(grams_x, grams_t, w_style, e_c)
+    msx = None if ms is None else ms.with_x(means_x)
+    terms = energy_terms(grams_x, grams_t, w_style, e_c, msx)
     terms["grams"] = grams_x
+    terms["means"] = means_x
     if not want_grad:
         return terms, None
     seeds = {}
     for k, i in enumerate(net.style):
         d = grams_x[k] - grams_t[k]
-        dt = q((2.0 * w_style[k] / n_ps[k]) * (d + d.T))
+        dt = (2.0 * w_style[k] / n_ps[k]) * (d + d.T)
+        b = None
+        if msx is not None:
+            r, b = ms_operands(grams_x[k], grams_t[k], means_x[k], msx.means_t[k], msx.w_mean[k], msx.w_std[k],
+                               n_ps[k])
+            dt = dt + np.diag(r)
+        dt = q(dt)
         c = acts[i].shape[0]
         seeds[i] = (dt @ acts[i].reshape(c, -1)).reshape(acts[i].shape)
+        if b is not None:
+            seeds[i] = seeds[i] + b[:, None, None]
     if net.content is not None and alpha != 0.0:
         cs = 2.0 * alpha * (raw[net.content] - f_c)
         seeds[net.content] = seeds.get(net.content, 0.0) + cs
@@ -112,3 +135,10 @@ def features(net: NetSpec, x, ws, bs, conv: int, q=round_bf16) -> np.ndarray:
 def style_grams(net: NetSpec, s_img, ws, bs, q=round_bf16):
     acts, _ = forward(net, s_img, ws, bs, q, upto=max(net.style))
     return [gram(acts[i], acts[i].shape[1] * acts[i].shape[2]) for i in net.style]
+
+
+def style_stats(net: NetSpec, s_img, ws, bs, q=round_bf16):
+    acts, _ = forward(net, s_img, ws, bs, q, upto=max(net.style))
+    n_ps = [acts[i].shape[1] * acts[i].shape[2] for i in net.style]
+    return ([gram(acts[i], n) for i, n in zip(net.style, n_ps)],
+            [channel_mean(acts[i], n) for i, n in zip(net.style, n_ps)])

@@ -5,4 +5,4 @@ include/nst.h).  ``nst`` is the thin Python binding; it refuses to run without t
 built library.
 """
 from .nst import (NST_BOTH, NST_CHECK_FINITE, NST_RESIDENT, NST_STEP1, NST_STEP2, NST_STRICT_HALO,  # noqa: F401
-                  Context, StyleEnergy, min_halo, plan, vgg19_desc, workspace_bytes)
+                  Context, MeanStdTerms, StyleEnergy, min_halo, plan, vgg19_desc, workspace_bytes)

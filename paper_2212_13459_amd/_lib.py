@@ -29,6 +29,11 @@ class Tile(ctypes.Structure):
                 ("own", (c_int * 4) * NST_MAX_CONV)]
 
 
+class MeanStd(ctypes.Structure):
+    _fields_ = [("w_mean", POINTER(c_double)), ("w_std", POINTER(c_double)), ("target_means", c_void_p),
+                ("means_x", c_void_p)]
+
+
 class KStat(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 160), ("launches", c_int), ("ms", c_double), ("flops", c_double),
                 ("bytes", c_double)]
@@ -66,6 +71,11 @@ SIGNATURES = {
     "nst_loss_grad": (c_int, [c_void_p, c_void_p, c_int, c_int, c_void_p, c_void_p, POINTER(c_double), c_double,
                               c_int, c_int, c_int, c_void_p, POINTER(c_double), c_void_p, c_void_p, c_size_t,
                               c_void_p]),
+    "nst_style_stats": (c_int, [c_void_p, c_void_p, c_int, c_int, c_int, c_int, c_void_p, c_void_p, c_void_p,
+                                c_size_t, c_void_p]),
+    "nst_loss_grad_ms": (c_int, [c_void_p, c_void_p, c_int, c_int, c_void_p, c_void_p, POINTER(c_double),
+                                 c_double, POINTER(MeanStd), c_int, c_int, c_int, c_void_p, POINTER(c_double),
+                                 c_void_p, c_void_p, c_size_t, c_void_p]),
 }
 
 

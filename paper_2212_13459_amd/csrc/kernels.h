@@ -46,7 +46,8 @@ struct ConvArgs {
   long long pool_ss;
   int cout;                    // real output channels
   int cout_pad;                // padded N of the packed operands
-  const float *bias;           // EPI_FWD
+  const float *bias;           // EPI_FWD: bias; EPI_BWD (optional): per-channel constant added
+                               // to the adjoint before the mask (mean/std seeds)
   const void *mask;            // EPI_BWD: keep where mask > 0 (post-ReLU activation, cout channels)
   long long mask_ss;
   float *rc;                   // content difference relu(acc) - F_c, fp32, cout channels
@@ -81,6 +82,11 @@ hipError_t launch_gram_tile_reduce(const float *part, long long part_ss, int C, 
                                    double *tilesum, hipStream_t s);
 hipError_t launch_gram_accum(const double *tilesum, int n_tiles, int C, double *gacc,
                              hipStream_t s);
+// csum[c] += sum of channel c over the owned region of each tile of g (chunks of kGramChunk
+// pixels, FP32 per chunk, FP64 per tile, added in tile order); part: per-slot scratch of
+// (chunks x C) floats
+hipError_t launch_chan_sums(int precision, const void *act, long long act_ss, int C, const Batch &g,
+                            float *part, long long part_ss, double *csum, hipStream_t s);
 hipError_t launch_content_partial(const float *rc, long long rc_ss, int C, const Batch &g,
                                   double *part, long long part_ss, hipStream_t s);
 hipError_t launch_content_accum(const double *part, long long part_ss, const Batch &g,
@@ -104,6 +110,11 @@ struct StyleTermsArgs {
   long long dt_off[8];         // element offset of layer l in the packed residual operand
   double w[8];
   double inv_np[8];
+  // augmented style loss (Eq. 5), when mx != nullptr
+  const double *mx, *mt;       // channel means of x and of the style image, concatenated
+  long long moff[8];           // offset of layer l in the concatenated means
+  double w1[8], w2[8];         // w'_l (mean) and w''_l (std)
+  float *msb;                  // out: per-channel constant of the mean/std seeds
 };
 // Energy terms w_l ||G_l - Ghat_l||^2 into e_style[l] and the packed residual operand
 // (2 w_l / n_p)(D + D^T) in compute precision.

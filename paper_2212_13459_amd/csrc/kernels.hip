@@ -225,6 +225,7 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a, Batch g) {
             a.rc[slot * a.rc_ss + pix * cout + n] = v - f;
           }
         } else if (EPI == EPI_BWD) {
+          if (a.bias) v += a.bias[n];
           if (a.rc) v += a.two_alpha * a.rc[slot * a.rc_ss + pix * cout + n];
           if (a.mask) {
             const float mk = to_f(((const T *)a.mask)[slot * a.mask_ss + pix * cout + n]);
@@ -343,6 +344,8 @@ __device__ __forceinline__ void epi_bf16(f32x16 (&acc)[PH * 32 / (WM * 32)][BN /
   typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
   typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
   const int cout = a.cout;
+  // backward: an optional per-channel constant joins the adjoint before the mask
+  const bool bwd_bias = EPI != EPI_FWD && a.bias != nullptr;
   // phase 1: block (tm, tn), lane: pixel l32, channels 8 jj + 4 half + (0..3) (mma_kstep)
 #pragma unroll
   for (int tn = 0; tn < TN; ++tn)
@@ -350,7 +353,7 @@ __device__ __forceinline__ void epi_bf16(f32x16 (&acc)[PH * 32 / (WM * 32)][BN /
     for (int jj = 0; jj < 4; ++jj) {
       const int cl = wn * TN * 32 + tn * 32 + 8 * jj + 4 * half;
       f32x4 b = {0.f, 0.f, 0.f, 0.f};
-      if constexpr (EPI == EPI_FWD) b = *(const f32x4 *)(a.bias + (n0 + cl < cout ? n0 + cl : 0));
+      if (EPI == EPI_FWD || bwd_bias) b = *(const f32x4 *)(a.bias + (n0 + cl < cout ? n0 + cl : 0));
 #pragma unroll
       for (int tm = 0; tm < TM; ++tm) {
         const int m = wm * TM * 32 + tm * 32 + l32;
@@ -359,6 +362,7 @@ __device__ __forceinline__ void epi_bf16(f32x16 (&acc)[PH * 32 / (WM * 32)][BN /
         for (int e = 0; e < 4; ++e) {
           float v = acc[tm][tn][4 * jj + e];
           if constexpr (EPI == EPI_FWD) v = fmaxf(v + b[e], 0.f);
+          else if (bwd_bias) v += b[e];
           o[e] = __builtin_bit_cast(unsigned short, (bf16)v);
           if constexpr (EPI == EPI_FWD) o[e] &= (unsigned short)0x7fff;
         }
@@ -490,6 +494,7 @@ __device__ __forceinline__ void conv_epilogue(f32x16 (&acc)[PH * 32 / (WM * 32)]
   static_assert(NW % GW == 0 && NIT % G == 0, "epilogue groups");
   const bool fwd_rc = EPI == EPI_FWD && a.rc != nullptr, bwd_rc = EPI != EPI_FWD && a.rc != nullptr;
   const bool bwd_mask = EPI != EPI_FWD && a.mask != nullptr;
+  const bool bwd_bias = EPI != EPI_FWD && a.bias != nullptr;
   // local (row, column) of item j of group g0
   auto item_fwd = [&](int k, int kk, int &ly, int &lx) __attribute__((always_inline)) {
     const int q = ib + k * QSTEP;
@@ -538,7 +543,7 @@ __device__ __forceinline__ void conv_epilogue(f32x16 (&acc)[PH * 32 / (WM * 32)]
     const bool nok = n < cout;
     const int nc = nok ? n : 0;
     float bv[VEC];
-    if constexpr (EPI == EPI_FWD) {
+    if (EPI == EPI_FWD || bwd_bias) {
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
         const f32x4 b = *(const f32x4 *)(a.bias + nc + 4 * q);
@@ -632,6 +637,10 @@ __device__ __forceinline__ void conv_epilogue(f32x16 (&acc)[PH * 32 / (WM * 32)]
           for (int q = 0; q < NQ; ++q) {
             const f32x4 u = *(const f32x4 *)(&so[m * RSW + lc + 4 * q]);
             v[4 * q] = u[0]; v[4 * q + 1] = u[1]; v[4 * q + 2] = u[2]; v[4 * q + 3] = u[3];
+          }
+          if (bwd_bias) {
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) v[e] += bv[e];
           }
           if (bwd_rc) {
 #pragma unroll
@@ -1686,11 +1695,81 @@ hipError_t launch_gram(int precision, const void *act, long long act_ss, int C, 
   }
   const int nb = C / 64;
   dim3 grid(nblk, nb * (nb + 1) / 2);
-  if (false)
-    ;
+  hipLaunchKernelGGL(k_gram<float>, grid, dim3(256), 0, s, (const float *)act, act_ss, C, g, part,
+                     part_ss);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------
+// Channel sums of the owned style features (the mean of Sec. 3.2, Algorithm 1 Step 1):
+// per 2048-pixel chunk of a tile's owned region (the Gram's chunks) an FP32 sum per channel,
+// then per tile an FP64 sum over its chunks in chunk order, added to the global sums in
+// tile order.  In a chunk, thread (pixel group pg, channel vector cg) adds pixels
+// pg, pg + PG, ... with 16-byte loads; the PG group sums are then added in group order.
+// ---------------------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_chan_partial(const T *act, long long act_ss, int C, Batch g,
+                                                      float *part, long long part_ss) {
+  constexpr int VEC = 16 / sizeof(T);
+  __shared__ float red[256 * VEC];
+  const int t = find_tile(g, blockIdx.x);
+  const int j = blockIdx.x - g.pfx[t];
+  const int w = g.w[t];
+  const int r0 = g.a0[t], c0 = g.a2[t], ow = g.a3[t] - g.a2[t];
+  const int npx = (g.a1[t] - r0) * ow;
+  const int p0 = j * kGramChunk, p1 = min(npx, p0 + kGramChunk);
+  const int cpv = C / VEC, pgs = 256 / cpv;          // threads per pixel, pixel groups
+  const int cg = threadIdx.x % cpv, pg = threadIdx.x / cpv;
+  const T *b = act + g.slot[t] * act_ss + cg * VEC;
+  float acc[VEC];
+#pragma unroll
+  for (int e = 0; e < VEC; ++e) acc[e] = 0.f;
+  if (pg < pgs) {
+    for (int p = p0 + pg; p < p1; p += pgs) {
+      const int y = r0 + p / ow, x = c0 + p % ow;
+      typedef T TV __attribute__((ext_vector_type(VEC)));
+      const TV v = *(const TV *)(b + ((long long)y * w + x) * C);
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) acc[e] += to_f(v[e]);
+    }
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) red[pg * C + cg * VEC + e] = acc[e];
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < C; c += 256) {
+    float s = 0.f;
+    for (int q = 0; q < pgs; ++q) s += red[q * C + c];
+    part[g.slot[t] * part_ss + (long long)j * C + c] = s;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_chan_accum(const float *part, long long part_ss, int C, Batch g,
+                                                    double *csum) {
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  if (c >= C) return;
+  double s = csum[c];
+  for (int t = 0; t < g.n; ++t) {
+    const float *q = part + g.slot[t] * part_ss + c;
+    double st = 0.0;
+    for (int j = 0; j < g.pfx[t + 1] - g.pfx[t]; ++j) st += (double)q[(long long)j * C];
+    s += st;
+  }
+  csum[c] = s;
+}
+
+hipError_t launch_chan_sums(int precision, const void *act, long long act_ss, int C, const Batch &g,
+                            float *part, long long part_ss, double *csum, hipStream_t s) {
+  const int nblk = g.pfx[g.n];
+  if (nblk == 0) return hipSuccess;
+  if (precision == 1)
+    hipLaunchKernelGGL(k_chan_partial<bf16>, dim3(nblk), dim3(256), 0, s, (const bf16 *)act, act_ss, C, g, part,
+                       part_ss);
   else
-    hipLaunchKernelGGL(k_gram<float>, grid, dim3(256), 0, s, (const float *)act, act_ss, C, g,
+    hipLaunchKernelGGL(k_chan_partial<float>, dim3(nblk), dim3(256), 0, s, (const float *)act, act_ss, C, g,
                        part, part_ss);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_chan_accum, dim3((C + 255) / 256), dim3(256), 0, s, part, part_ss, C, g, csum);
   return hipGetLastError();
 }
 
@@ -1938,7 +2017,28 @@ __global__ __launch_bounds__(256) void k_style_energy(const double *g, const dou
     if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
     __syncthreads();
   }
-  if (threadIdx.x == 0) e_style[l] = a.w[l] * red[0];
+  double el = a.w[l] * red[0];
+  if (a.mx) {
+    // Eq. 5: w' ||mean_x - mean_t||^2 + w'' ||std_x - std_t||^2, std = (diag G - mean^2)^(1/2)
+    __syncthreads();
+    const double *mx = a.mx + a.moff[l], *mt = a.mt + a.moff[l];
+    double sm = 0.0, ss = 0.0;
+    for (int c = threadIdx.x; c < C; c += 256) {
+      const double dm = mx[c] - mt[c];
+      const double sx = sqrt(fmax(G[(long long)c * C + c] - mx[c] * mx[c], 0.0));
+      const double st = sqrt(fmax(H[(long long)c * C + c] - mt[c] * mt[c], 0.0));
+      sm += dm * dm;
+      ss += (sx - st) * (sx - st);
+    }
+    red[threadIdx.x] = a.w1[l] * sm + a.w2[l] * ss;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+      __syncthreads();
+    }
+    el += red[0];
+  }
+  if (threadIdx.x == 0) e_style[l] = el;
 }
 
 template <typename T>
@@ -1956,7 +2056,20 @@ __global__ __launch_bounds__(256) void k_style_pack(const double *g, const doubl
   const double coef = 2.0 * a.w[l] * a.inv_np[l];
   const double dij = G[(long long)i * C + j] - H[(long long)i * C + j];
   const double dji = G[(long long)j * C + i] - H[(long long)j * C + i];
-  dt[a.dt_off[l] + u] = from_f<T>((float)(coef * (dij + dji)));
+  double v = coef * (dij + dji);
+  if (a.mx && i == j) {
+    // Table 1 rows 3-4: the std seed (2 w'' / n_p)(V - mean)(std - std_t) / std is
+    // V diag(r) - mean r with r = (2 w'' / n_p)(std - std_t) / std (0 where std = 0); diag(r)
+    // joins the residual operand, and the per-channel rest, with the mean seed
+    // (2 w' / n_p)(mean - mean_t), is the constant ms added to every pixel's adjoint
+    const double mx = a.mx[a.moff[l] + i], mt = a.mt[a.moff[l] + i];
+    const double sx = sqrt(fmax(G[(long long)i * C + i] - mx * mx, 0.0));
+    const double st = sqrt(fmax(H[(long long)i * C + i] - mt * mt, 0.0));
+    const double r = sx > 0.0 ? 2.0 * a.w2[l] * a.inv_np[l] * (sx - st) / sx : 0.0;
+    v += r;
+    a.msb[a.moff[l] + i] = (float)(2.0 * a.w1[l] * a.inv_np[l] * (mx - mt) - r * mx);
+  }
+  dt[a.dt_off[l] + u] = from_f<T>((float)v);
 }
 
 hipError_t launch_style_terms(int precision, const double *g, const double *gt,

@@ -151,13 +151,17 @@ struct Layout {
   size_t es = 4;
   // global region
   size_t g_gacc = 0, g_dt = 0, g_estyle = 0, g_ec = 0, g_energy = 0, g_tilesum = 0, g_flag = 0;
+  size_t g_csum = 0, g_msb = 0;  // channel sums (FP64) and mean/std seed constants (FP32)
   long long total_cc = 0;       // sum over style layers of C_l^2
+  long long total_c = 0;        // sum over style layers of C_l
+  long long moff[NST_MAX_STYLE] = {};
   long long off_c[NST_MAX_STYLE] = {}, dt_off[NST_MAX_STYLE] = {};
   size_t slots = 0, slot_bytes = 0;
   // per-slot offsets
   size_t s_act[NST_MAX_CONV] = {}, s_pool[NST_MAX_CONV] = {};
   size_t s_d0 = 0, s_d1 = 0, s_rc = 0, s_cpart = 0;
   size_t s_gpart[NST_MAX_STYLE] = {};
+  size_t s_mpart[NST_MAX_STYLE] = {};
 };
 
 // Element offsets are 64-bit everywhere; the 32-bit quantity is a launch's work-item
@@ -230,6 +234,16 @@ void make_layout(const Geom &g, int precision, const std::vector<nst_tile> &tile
   L.g_flag = off;
   off = al(off + 8);
   L.total_cc = cc;
+  long long csz = 0;
+  for (int k = 0; k < g.n_style; ++k) {
+    L.moff[k] = csz;
+    csz += g.cout[g.style[k]];
+  }
+  L.total_c = csz;
+  L.g_csum = off;
+  off = al(off + csz * 8);
+  L.g_msb = off;
+  off = al(off + csz * 4);
   L.slots = off;
   // per slot
   size_t so = 0, dmax = 0;
@@ -257,6 +271,8 @@ void make_layout(const Geom &g, int precision, const std::vector<nst_tile> &tile
     const int C = g.cout[g.style[k]];
     L.s_gpart[k] = so;
     so = al(so + (size_t)L.gchunks[k] * C * C * 4);
+    L.s_mpart[k] = so;
+    so = al(so + (size_t)L.gchunks[k] * C * 4);
   }
   L.slot_bytes = so;
   L.total = L.slots + (size_t)nslots * L.slot_bytes;
@@ -674,7 +690,8 @@ struct Runner {
     return NST_OK;
   }
 
-  int grams(int first, int n) {
+  // Grams of the owned features (and, with means, their channel sums) of tiles first..+n
+  int grams(int first, int n, bool means) {
     for (int k = 0; k < g.n_style; ++k) {
       const int i = g.style[k], C = g.cout[i];
       Batch b = base_batch(first, n, i);
@@ -693,6 +710,14 @@ struct Runner {
       HIPCHK(launch_gram_tile_reduce(part, ss(4), C, b, gl<double>(L.g_tilesum), s));
       HIPCHK(launch_gram_accum(gl<double>(L.g_tilesum), n, C,
                                gl<double>(L.g_gacc) + L.off_c[k], s));
+      if (means)
+        HIPCHK(prof(c->prec == 1 ? "void nst::k_chan_partial<__bf16>(__bf16 const*, long long, int, nst::Batch, float*, long long)"
+                                 : "void nst::k_chan_partial<float>(float const*, long long, int, nst::Batch, float*, long long)",
+                    0.0, npx * C * L.es, [&] {
+                      return launch_chan_sums(c->prec, slot_base(L.s_act[i]), ss(L.es), C, b,
+                                              (float *)slot_base(L.s_mpart[k]), ss(4),
+                                              gl<double>(L.g_csum) + L.moff[k], s);
+                    }));
     }
     return NST_OK;
   }
@@ -709,7 +734,7 @@ struct Runner {
     return NST_OK;
   }
 
-  int backward(int first, int n, float two_alpha, bool use_content, float *grad) {
+  int backward(int first, int n, float two_alpha, bool use_content, bool use_ms, float *grad) {
     const size_t es = L.es;
     const int vec = (int)(16 / es);
     char *cur = slot_base(L.s_d0), *oth = slot_base(L.s_d1);
@@ -724,6 +749,7 @@ struct Runner {
         a.in2_ss = ss(es);
         a.cin2 = g.cout[j];
         a.wp2 = gl<char>(L.g_dt) + (size_t)L.dt_off[k] * es;
+        if (use_ms) a.bias = gl<float>(L.g_msb) + L.moff[k];
       }
       if (j == g.content && use_content) {
         a.rc = (float *)slot_base(L.s_rc);
@@ -849,11 +875,12 @@ int setup(Runner &R, nst_ctx *ctx, int H, int W, int T, int m, void *ws, size_t 
 }
 
 // keep: also store full-resolution activations of pooled layers (for a Step 2 that
-// reuses this pass's activations)
-int step1(Runner &R, const float *x, const float *fc, bool keep) {
+// reuses this pass's activations); means: also sum the style features' channels
+int step1(Runner &R, const float *x, const float *fc, bool keep, bool means) {
   const Geom &g = R.g;
   HIPCHK(launch_fill_f64(R.gl<double>(R.L.g_gacc), (R.L.g_dt - R.L.g_gacc) / 8, 0.0, R.s));
   HIPCHK(launch_fill_f64(R.gl<double>(R.L.g_ec), 1, 0.0, R.s));
+  if (means) HIPCHK(launch_fill_f64(R.gl<double>(R.L.g_csum), (size_t)R.L.total_c, 0.0, R.s));
   int upto = -1;
   for (int k = 0; k < g.n_style; ++k) upto = std::max(upto, g.style[k]);
   if (fc) upto = std::max(upto, g.content);
@@ -862,19 +889,23 @@ int step1(Runner &R, const float *x, const float *fc, bool keep) {
     const int n = std::min(R.L.batch, nt - first);
     int st = R.forward(first, n, upto, x, fc, keep);
     if (st != NST_OK) return st;
-    if ((st = R.grams(first, n)) != NST_OK) return st;
+    if ((st = R.grams(first, n, means)) != NST_OK) return st;
     if (fc && (st = R.content_energy(first, n)) != NST_OK) return st;
   }
   return NST_OK;
 }
 
-int normalize(Runner &R, double *grams_out) {
+// Grams (and channel means) divided by the whole-image n_p (Sec. 3.1, 3.2)
+int normalize(Runner &R, double *grams_out, double *means_out) {
   const Geom &g = R.g;
   for (int k = 0; k < g.n_style; ++k) {
     const int i = g.style[k], C = g.cout[i];
     const double np = (double)(R.H / g.stride[i]) * (double)(R.W / g.stride[i]);
     HIPCHK(launch_gram_normalize(R.gl<double>(R.L.g_gacc) + R.L.off_c[k],
                                  grams_out + R.L.off_c[k], (size_t)C * C, np, R.s));
+    if (means_out)
+      HIPCHK(launch_gram_normalize(R.gl<double>(R.L.g_csum) + R.L.moff[k], means_out + R.L.moff[k],
+                                   (size_t)C, np, R.s));
   }
   return NST_OK;
 }
@@ -925,15 +956,20 @@ int nst_profile_read(nst_ctx *ctx, nst_kstat *out, int cap, int *n) {
   return st;
 }
 
-int nst_style_grams(nst_ctx *ctx, const float *s, int H, int W, int T, int m, double *grams,
-                    void *ws, size_t ws_bytes, void *stream) {
+int nst_style_stats(nst_ctx *ctx, const float *s, int H, int W, int T, int m, double *grams,
+                    double *means, void *ws, size_t ws_bytes, void *stream) {
   if (!ctx || !s || !grams) return NST_EINVAL;
   if (ctx->g.n_style == 0) return NST_EINVAL;
   Runner R(ctx);
   int st = setup(R, ctx, H, W, T, m, ws, ws_bytes, stream, 0);
   if (st != NST_OK) return st;
-  if ((st = step1(R, s, nullptr, false)) != NST_OK) return st;
-  return normalize(R, grams);
+  if ((st = step1(R, s, nullptr, false, means != nullptr)) != NST_OK) return st;
+  return normalize(R, grams, means);
+}
+
+int nst_style_grams(nst_ctx *ctx, const float *s, int H, int W, int T, int m, double *grams,
+                    void *ws, size_t ws_bytes, void *stream) {
+  return nst_style_stats(ctx, s, H, W, T, m, grams, nullptr, ws, ws_bytes, stream);
 }
 
 int nst_layer_feats(nst_ctx *ctx, const float *img, int H, int W, int T, int m, int conv,
@@ -965,10 +1001,10 @@ int nst_content_feats(nst_ctx *ctx, const float *c, int H, int W, int T, int m, 
   return nst_layer_feats(ctx, c, H, W, T, m, ctx->g.content, feats, ws, ws_bytes, stream);
 }
 
-int nst_loss_grad(nst_ctx *ctx, const float *x, int H, int W, const double *target_grams,
-                  const float *content_feats, const double *w_style, double alpha, int T, int m,
-                  int flags, double *grams_x, double *energy, float *grad, void *ws,
-                  size_t ws_bytes, void *stream) {
+int nst_loss_grad_ms(nst_ctx *ctx, const float *x, int H, int W, const double *target_grams,
+                     const float *content_feats, const double *w_style, double alpha,
+                     const nst_mean_std *ms, int T, int m, int flags, double *grams_x,
+                     double *energy, float *grad, void *ws, size_t ws_bytes, void *stream) {
   if (!ctx || !x || !grams_x) return NST_EINVAL;
   if ((flags & ~(NST_BOTH | NST_STRICT_HALO | NST_RESIDENT | NST_CHECK_FINITE)) != 0 ||
       (flags & NST_BOTH) == 0)
@@ -979,6 +1015,8 @@ int nst_loss_grad(nst_ctx *ctx, const float *x, int H, int W, const double *targ
   if (use_c && !content_feats) return NST_EINVAL;
   if (g.n_style > 0 && (!target_grams || !w_style)) return NST_EINVAL;
   if (s2 && !grad) return NST_EINVAL;
+  const bool use_ms = ms != nullptr && g.n_style > 0;
+  if (use_ms && (!ms->w_mean || !ms->w_std || !ms->target_means || !ms->means_x)) return NST_EINVAL;
   Runner R(ctx);
   int st = setup(R, ctx, H, W, T, m, ws, ws_bytes, stream, flags);
   if (st != NST_OK) return st;
@@ -995,12 +1033,18 @@ int nst_loss_grad(nst_ctx *ctx, const float *x, int H, int W, const double *targ
     }
     if (g.n_style > 0) HIPCHK(launch_count_nonfinite_f64(target_grams, (size_t)R.L.total_cc, cnt, R.s));
     if (!s1) HIPCHK(launch_count_nonfinite_f64(grams_x, (size_t)R.L.total_cc, cnt, R.s));
+    if (use_ms) {
+      HIPCHK(launch_count_nonfinite_f64(ms->target_means, (size_t)R.L.total_c, cnt, R.s));
+      if (!s1) HIPCHK(launch_count_nonfinite_f64(ms->means_x, (size_t)R.L.total_c, cnt, R.s));
+    }
     unsigned host_cnt = 0;
     HIPCHK(hipMemcpyAsync(&host_cnt, cnt, sizeof(unsigned), hipMemcpyDeviceToHost, R.s));
     HIPCHK(hipStreamSynchronize(R.s));
     if (host_cnt != 0) return NST_ENONFINITE;
-    for (int k = 0; k < g.n_style; ++k)
+    for (int k = 0; k < g.n_style; ++k) {
       if (!std::isfinite(w_style[k])) return NST_ENONFINITE;
+      if (use_ms && (!std::isfinite(ms->w_mean[k]) || !std::isfinite(ms->w_std[k]))) return NST_ENONFINITE;
+    }
     if (!std::isfinite(alpha)) return NST_ENONFINITE;
   }
 
@@ -1014,11 +1058,21 @@ int nst_loss_grad(nst_ctx *ctx, const float *x, int H, int W, const double *targ
     sa.dt_off[k] = R.L.dt_off[k];
     sa.w[k] = w_style[k];
     sa.inv_np[k] = 1.0 / ((double)(H / g.stride[i]) * (double)(W / g.stride[i]));
+    sa.moff[k] = R.L.moff[k];
+    if (use_ms) {
+      sa.w1[k] = ms->w_mean[k];
+      sa.w2[k] = ms->w_std[k];
+    }
+  }
+  if (use_ms) {
+    sa.mx = ms->means_x;
+    sa.mt = ms->target_means;
+    sa.msb = R.gl<float>(R.L.g_msb);
   }
 
   if (s1) {
-    if ((st = step1(R, x, fc, R.retain && s2)) != NST_OK) return st;
-    if ((st = normalize(R, grams_x)) != NST_OK) return st;
+    if ((st = step1(R, x, fc, R.retain && s2, use_ms)) != NST_OK) return st;
+    if ((st = normalize(R, grams_x, use_ms ? ms->means_x : nullptr)) != NST_OK) return st;
   } else {
     HIPCHK(launch_fill_f64(R.gl<double>(R.L.g_ec), 1, 0.0, R.s));
   }
@@ -1033,7 +1087,7 @@ int nst_loss_grad(nst_ctx *ctx, const float *x, int H, int W, const double *targ
       // slot when each tile has one; otherwise Step 2 recomputes them (Algorithm 1)
       if (!(s1 && R.retain) && (st = R.forward(first, n, g.top, x, fc, true)) != NST_OK) return st;
       if (!s1 && fc && (st = R.content_energy(first, n)) != NST_OK) return st;
-      if ((st = R.backward(first, n, (float)(2.0 * alpha), use_c, grad)) != NST_OK) return st;
+      if ((st = R.backward(first, n, (float)(2.0 * alpha), use_c, use_ms, grad)) != NST_OK) return st;
     }
   }
   HIPCHK(launch_energy_total(R.gl<double>(R.L.g_ec), R.gl<double>(R.L.g_estyle), g.n_style,
@@ -1044,6 +1098,14 @@ int nst_loss_grad(nst_ctx *ctx, const float *x, int H, int W, const double *targ
     HIPCHK(hipStreamSynchronize(R.s));
   }
   return NST_OK;
+}
+
+int nst_loss_grad(nst_ctx *ctx, const float *x, int H, int W, const double *target_grams,
+                  const float *content_feats, const double *w_style, double alpha, int T, int m,
+                  int flags, double *grams_x, double *energy, float *grad, void *ws,
+                  size_t ws_bytes, void *stream) {
+  return nst_loss_grad_ms(ctx, x, H, W, target_grams, content_feats, w_style, alpha, nullptr, T, m,
+                          flags, grams_x, energy, grad, ws, ws_bytes, stream);
 }
 
 }  // extern "C"

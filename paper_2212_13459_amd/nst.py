@@ -12,7 +12,7 @@ import numpy as np
 import torch
 
 from ._lib import (NST_BF16, NST_BOTH, NST_CHECK_FINITE, NST_FP32, NST_RESIDENT, NST_STEP1, NST_STEP2,
-                   NST_STRICT_HALO, NetDesc, Tile, check, lib)
+                   NST_STRICT_HALO, MeanStd, NetDesc, Tile, check, lib)
 
 PRECISIONS = {"fp32": NST_FP32, "bf16": NST_BF16}
 
@@ -64,6 +64,24 @@ def _ptr(t: torch.Tensor):
 
 def _stream(dev):
     return c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+
+
+class MeanStdTerms:
+    """Weights and statistics of the mean and std terms of the augmented style loss
+    (Eq. 5): w_mean = w'_l and w_std = w''_l per style layer, target_means = the style
+    image's channel means (Context.style_stats), means_x = the channel means of x
+    (written by Step 1, read by a Step-2-only call; allocated on first use)."""
+
+    def __init__(self, w_mean, w_std, target_means: torch.Tensor, means_x: torch.Tensor | None = None):
+        self.w_mean, self.w_std = list(w_mean), list(w_std)
+        self.target_means, self.means_x = target_means, means_x
+
+    def _struct(self, n_style):
+        if self.means_x is None:
+            self.means_x = torch.empty_like(self.target_means)
+        self._wm = (c_double * max(n_style, 1))(*[float(v) for v in self.w_mean])
+        self._wsd = (c_double * max(n_style, 1))(*[float(v) for v in self.w_std])
+        return MeanStd(self._wm, self._wsd, _ptr(self.target_means), _ptr(self.means_x))
 
 
 class Context:
@@ -168,6 +186,24 @@ class Context:
                                                        ws.numel(), _stream(self.device)))
         return g
 
+    def style_stats(self, s: torch.Tensor, T: int, m: int):
+        """(Grams, channel means) of the style layers of image s (nst_style_stats)."""
+        s = self._img(s)
+        H, W = s.shape[1:]
+        g = torch.empty(sum(c * c for c in self.gram_sizes()), dtype=torch.float64, device=self.device)
+        mu = torch.empty(sum(self.gram_sizes()), dtype=torch.float64, device=self.device)
+        ws = self.workspace(H, W, T, m)
+        check("nst_style_stats", lib().nst_style_stats(self._h, _ptr(s), H, W, T, m, _ptr(g), _ptr(mu), _ptr(ws),
+                                                       ws.numel(), _stream(self.device)))
+        return g, mu
+
+    def split_means(self, flat: torch.Tensor):
+        out, o = [], 0
+        for c in self.gram_sizes():
+            out.append(flat[o:o + c])
+            o += c
+        return out
+
     def layer_feats(self, img: torch.Tensor, T: int, m: int, conv: int) -> torch.Tensor:
         img = self._img(img)
         H, W = img.shape[1:]
@@ -189,8 +225,10 @@ class Context:
         return f
 
     def loss_grad(self, x, target_grams, content_feats, w_style, alpha, T, m, flags=NST_BOTH,
-                  grams_x=None, want_energy=True, grad=None):
-        """Returns (energy list [E, E_content, E_style...] or None, grams_x, grad or None)."""
+                  grams_x=None, want_energy=True, grad=None, ms: MeanStdTerms | None = None):
+        """Returns (energy list [E, E_content, E_style...] or None, grams_x, grad or None).
+        With ms (MeanStdTerms) the style terms are the augmented ones of Eq. 5 and ms.means_x
+        receives the channel means of x."""
         x = self._img(x)
         H, W = x.shape[1:]
         if grams_x is None:
@@ -204,10 +242,17 @@ class Context:
         cf = _ptr(content_feats) if content_feats is not None else c_void_p()
         if self.resident:
             flags |= NST_RESIDENT
-        check("nst_loss_grad", lib().nst_loss_grad(
-            self._h, _ptr(x), H, W, _ptr(target_grams), cf, wst, float(alpha), T, m, flags, _ptr(grams_x),
-            en if want_energy else None, _ptr(grad) if grad is not None else c_void_p(), _ptr(ws), ws.numel(),
-            _stream(self.device)))
+        if ms is None:
+            check("nst_loss_grad", lib().nst_loss_grad(
+                self._h, _ptr(x), H, W, _ptr(target_grams), cf, wst, float(alpha), T, m, flags, _ptr(grams_x),
+                en if want_energy else None, _ptr(grad) if grad is not None else c_void_p(), _ptr(ws), ws.numel(),
+                _stream(self.device)))
+        else:
+            st = ms._struct(ns)
+            check("nst_loss_grad_ms", lib().nst_loss_grad_ms(
+                self._h, _ptr(x), H, W, _ptr(target_grams), cf, wst, float(alpha), byref(st), T, m, flags,
+                _ptr(grams_x), en if want_energy else None, _ptr(grad) if grad is not None else c_void_p(),
+                _ptr(ws), ws.numel(), _stream(self.device)))
         energy = list(en) if want_energy else None
         return energy, grams_x, (grad if flags & NST_STEP2 else None)
 
@@ -217,20 +262,23 @@ class StyleEnergy(torch.autograd.Function):
     Step 2 from the saved Grams, recomputing each tile's activations."""
 
     @staticmethod
-    def forward(ctx, x, nst: Context, target_grams, content_feats, w_style, alpha, T, m):
-        energy, grams_x, _ = nst.loss_grad(x, target_grams, content_feats, w_style, alpha, T, m, flags=NST_STEP1)
+    def forward(ctx, x, nst: Context, target_grams, content_feats, w_style, alpha, T, m, ms=None):
+        if ms is not None:
+            ms = MeanStdTerms(ms.w_mean, ms.w_std, ms.target_means)
+        energy, grams_x, _ = nst.loss_grad(x, target_grams, content_feats, w_style, alpha, T, m, flags=NST_STEP1,
+                                           ms=ms)
         ctx.save_for_backward(x, grams_x)
-        ctx.args = (nst, target_grams, content_feats, w_style, alpha, T, m)
+        ctx.args = (nst, target_grams, content_feats, w_style, alpha, T, m, ms)
         return torch.tensor(energy[0], dtype=torch.float64, device=x.device)
 
     @staticmethod
     def backward(ctx, g_e):
         x, grams_x = ctx.saved_tensors
-        nst, target_grams, content_feats, w_style, alpha, T, m = ctx.args
+        nst, target_grams, content_feats, w_style, alpha, T, m, ms = ctx.args
         _, _, grad = nst.loss_grad(x, target_grams, content_feats, w_style, alpha, T, m, flags=NST_STEP2,
-                                   grams_x=grams_x, want_energy=False)
-        return g_e.to(grad.dtype) * grad, None, None, None, None, None, None, None
+                                   grams_x=grams_x, want_energy=False, ms=ms)
+        return g_e.to(grad.dtype) * grad, None, None, None, None, None, None, None, None
 
 
-__all__ = ["Context", "StyleEnergy", "vgg19_desc", "min_halo", "plan", "workspace_bytes", "NST_STEP1",
+__all__ = ["Context", "StyleEnergy", "MeanStdTerms", "vgg19_desc", "min_halo", "plan", "workspace_bytes", "NST_STEP1",
            "NST_STEP2", "NST_BOTH", "NST_STRICT_HALO", "NST_CHECK_FINITE", "NST_RESIDENT"]

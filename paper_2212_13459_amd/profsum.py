@@ -18,6 +18,7 @@ import csv
 import glob
 import hashlib
 import os
+import re
 import sqlite3
 import subprocess
 import sys
@@ -28,15 +29,17 @@ COPY_KERNEL = "neg_kernel"
 
 
 def demangle(names):
-    """Demangled kernel names.  rocprofv3 leaves names with a __bf16 template argument
-    mangled (its demangler does not know DF16b); spelled as the vendor type u6__bf16
-    they demangle to the same text as the library's own profile records."""
+    """Demangled kernel names.  The demanglers here do not know the __bf16 code DF16b;
+    it is read as the half-precision code Dh (like it, a builtin type that takes no
+    substitution slot, so later back-references keep their meaning) and the type name
+    is written back, which gives the text of the library's own profile records."""
     names = list(names)
     todo = [n for n in names if n.startswith("_Z")]
     if not todo:
         return {n: n for n in names}
-    out = subprocess.run(["c++filt"], input="\n".join(t.replace("DF16b", "u6__bf16") for t in todo),
+    out = subprocess.run(["c++filt"], input="\n".join(t.replace("DF16b", "Dh") for t in todo),
                          capture_output=True, text=True, check=True).stdout.split("\n")
+    out = [re.sub(r"\bhalf\b", "__bf16", o) for o in out]
     m = {n: n for n in names}
     m.update(zip(todo, out))
     return m
@@ -150,34 +153,59 @@ def read_traffic(profiles_dir, kernel):
     return None
 
 
+def dispatches(path):
+    """[(demangled kernel name, start ns, duration ns)] in start order, from a kernel trace:
+    kernel_trace.csv or a rocpd database (*_results.db)."""
+    out = []
+    try:
+        f = _find(path, "*kernel_trace.csv")
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                out.append((r["Kernel_Name"], int(r["Start_Timestamp"]),
+                            int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
+    except FileNotFoundError:
+        # the mangled symbol name (rocprofv3's own demangled name garbles a __bf16 argument)
+        con = sqlite3.connect(_find(path, "*_results.db"))
+        q = ("select coalesce(s.kernel_name, k.name), k.start, k.end from kernels k "
+             "left join kernel_symbols s on s.kernel_id = k.kernel_id")
+        out = [(n[:-3] if n.endswith(".kd") else n, int(a), int(b) - int(a)) for n, a, b in con.execute(q)]
+    dm = demangle({n for n, _, _ in out})
+    return sorted(((dm[n], a, d) for n, a, d in out), key=lambda r: r[1])
+
+
 def last_dispatches(path, kernel, n):
-    """Mean duration (ms) of the last n dispatches of ``kernel`` in kernel_trace.csv."""
-    f = _find(path, "*kernel_trace.csv")
-    d = []
-    with open(f) as fh:
-        rows = list(csv.DictReader(fh))
-    dm = demangle({r["Kernel_Name"] for r in rows})
-    for row in rows:
-        if kernel in dm[row["Kernel_Name"]]:
-            d.append((int(row["Start_Timestamp"]), int(row["End_Timestamp"]) - int(row["Start_Timestamp"])))
-    d.sort()
-    tail = [x[1] for x in d[-n:]]
+    """Mean duration (ms) of the last n dispatches of ``kernel``."""
+    d = [x for x in dispatches(path) if kernel in x[0]]
+    tail = [x[2] for x in d[-n:]]
     return len(d), sum(tail) / len(tail) / 1e6
 
 
+def _agg(path):
+    """Per kernel: calls, total, average, min, max (ns) and percentage of the summed time."""
+    try:
+        f = _find(path, "*kernel_stats.csv")
+        with open(f) as fh:
+            rows = list(csv.DictReader(fh))
+        dm = demangle({r["Name"] for r in rows})
+        return [(dm[r["Name"]], int(r["Calls"]), float(r["TotalDurationNs"]), float(r["AverageNs"]),
+                 float(r["MinNs"]), float(r["MaxNs"]), float(r["Percentage"])) for r in rows]
+    except FileNotFoundError:
+        agg = collections.OrderedDict()
+        for name, _, d in dispatches(path):
+            agg.setdefault(name, []).append(d)
+        tot = sum(sum(v) for v in agg.values()) or 1.0
+        return [(k, len(v), float(sum(v)), sum(v) / len(v), float(min(v)), float(max(v)), 100.0 * sum(v) / tot)
+                for k, v in agg.items()]
+
+
 def stats(path, top, cmd, kernel="", last=0):
-    f = _find(path, "*kernel_stats.csv")
-    with open(f) as fh:
-        rows = list(csv.DictReader(fh))
-    dm = demangle({r["Name"] for r in rows})
-    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    rows = sorted(_agg(path), key=lambda r: -r[2])
     lines = [f"command: {cmd}", "",
              "| kernel | calls | total ms | average ms | min ms | max ms | % |",
              "|---|---:|---:|---:|---:|---:|---:|"]
-    for r in rows[:top]:
-        lines.append(f"| `{dm[r['Name']][:110]}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
-                     f"{float(r['AverageNs']) / 1e6:.4f} | {float(r['MinNs']) / 1e6:.4f} | "
-                     f"{float(r['MaxNs']) / 1e6:.4f} | {float(r['Percentage']):.2f} |")
+    for name, calls, tot, avg, mn, mx, pct in rows[:top]:
+        lines.append(f"| `{name[:110]}` | {calls} | {tot / 1e6:.3f} | {avg / 1e6:.4f} | {mn / 1e6:.4f} | "
+                     f"{mx / 1e6:.4f} | {pct:.2f} |")
     if kernel and last:
         total, avg = last_dispatches(path, kernel, last)
         lines += ["", f"`{kernel}`: {total} dispatches in the run; mean of the last {last} "

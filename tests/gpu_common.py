@@ -7,7 +7,7 @@ import torch
 import oracle
 import synth
 from oracle import bf16ref
-from oracle.loss import content_features, loss_grad, style_grams
+from oracle.loss import MeanStd, content_features, loss_grad, style_grams, style_stats
 from oracle.ops import conv3x3, maxpool2, relu
 
 
@@ -46,24 +46,41 @@ def oracle_targets(kind, H, W, Hs, Ws, sigma, bias=0.0):
     return g_t, f_c
 
 
+@functools.lru_cache(maxsize=None)
+def oracle_style_means(kind, H, W, Hs, Ws, sigma, bias=0.0):
+    """Channel means of the style image's style layers (FP64 oracle)."""
+    k = case(kind, H, W, Hs, Ws, sigma, bias)
+    ws = [w.astype(np.float64) for w in k["ws"]]
+    bs = [b.astype(np.float64) for b in k["bs"]]
+    return style_stats(k["net"], k["s"].astype(np.float64), ws, bs)[1]
+
+
+def mean_std(spec, msw, bias=0.0):
+    """oracle.loss.MeanStd for weights msw = (w_mean tuple, w_std tuple), or None."""
+    if msw is None:
+        return None
+    return MeanStd(msw[0], msw[1], oracle_style_means(*spec, bias))
+
+
 _records = {}
 
 
 @functools.lru_cache(maxsize=None)
-def oracle_loss(kind, H, W, Hs, Ws, sigma, w_style, alpha, bias=0.0):
+def oracle_loss(kind, H, W, Hs, Ws, sigma, w_style, alpha, bias=0.0, msw=None):
     k = case(kind, H, W, Hs, Ws, sigma, bias)
     net = k["net"]
     ws = [w.astype(np.float64) for w in k["ws"]]
     bs = [b.astype(np.float64) for b in k["bs"]]
     g_t, f_c = oracle_targets(kind, H, W, Hs, Ws, sigma, bias)
     rec = {}
-    terms, grad = loss_grad(net, k["x"].astype(np.float64), ws, bs, g_t, f_c, list(w_style), alpha, record=rec)
-    _records[(kind, H, W, Hs, Ws, sigma, w_style, alpha, bias)] = rec
+    terms, grad = loss_grad(net, k["x"].astype(np.float64), ws, bs, g_t, f_c, list(w_style), alpha, record=rec,
+                            ms=mean_std((kind, H, W, Hs, Ws, sigma), msw, bias))
+    _records[(kind, H, W, Hs, Ws, sigma, w_style, alpha, bias, msw)] = rec
     return terms, grad
 
 
 @functools.lru_cache(maxsize=None)
-def bf16ref_loss(kind, H, W, Hs, Ws, sigma, w_style, alpha, bias=0.0):
+def bf16ref_loss(kind, H, W, Hs, Ws, sigma, w_style, alpha, bias=0.0, msw=None):
     """The BF16-storage reference (oracle/bf16ref.py) on the oracle's FP64 targets."""
     from oracle import bf16ref
     k = case(kind, H, W, Hs, Ws, sigma, bias)
@@ -71,15 +88,16 @@ def bf16ref_loss(kind, H, W, Hs, Ws, sigma, w_style, alpha, bias=0.0):
     bs = [b.astype(np.float64) for b in k["bs"]]
     g_t, f_c = oracle_targets(kind, H, W, Hs, Ws, sigma, bias)
     f_c32 = f_c.astype(np.float32).astype(np.float64)
-    return bf16ref.loss_grad(k["net"], k["x"].astype(np.float64), ws, bs, g_t, f_c32, list(w_style), alpha)
+    return bf16ref.loss_grad(k["net"], k["x"].astype(np.float64), ws, bs, g_t, f_c32, list(w_style), alpha,
+                             ms=mean_std((kind, H, W, Hs, Ws, sigma), msw, bias))
 
 
-def flip_corrected(kind, H, W, Hs, Ws, sigma, w_style, alpha, g_test, bias=0.0, delta=1e-5):
+def flip_corrected(kind, H, W, Hs, Ws, sigma, w_style, alpha, g_test, bias=0.0, delta=1e-5, msw=None):
     """Residual of g_test after removing the exact effects of flipped near-tie decisions
     (decisions whose FP64 margin is below delta x RMS); see oracle.flips."""
     from oracle.flips import flip_fit
-    terms, g_ref = oracle_loss(kind, H, W, Hs, Ws, sigma, w_style, alpha, bias)
-    rec = _records[(kind, H, W, Hs, Ws, sigma, w_style, alpha, bias)]
+    terms, g_ref = oracle_loss(kind, H, W, Hs, Ws, sigma, w_style, alpha, bias, msw)
+    rec = _records[(kind, H, W, Hs, Ws, sigma, w_style, alpha, bias, msw)]
     k = case(kind, H, W, Hs, Ws, sigma, bias)
     ws = [w.astype(np.float64) for w in k["ws"]]
     bs = [b.astype(np.float64) for b in k["bs"]]
@@ -153,18 +171,28 @@ def check_forward(net, acts, ws, bs, x, prec, label):
     return worst
 
 
-def seeds_on(net, acts, raw_c, grams_x, g_t, f_c, w_style, alpha, prec, n_ps=None):
+def seeds_on(net, acts, raw_c, grams_x, g_t, f_c, w_style, alpha, prec, n_ps=None, ms=None):
     """Table 1 seeds on the given activations: style (2 w / n_p)(D + D^T) stored in the
-    compute precision, content 2 alpha (V - F_c) from the unrounded content value.
-    n_ps: whole-image feature counts per style layer (default: those of ``acts``)."""
+    compute precision (with ms, an oracle.loss.MeanStd holding the means of x, plus
+    diag(r) and the per-channel constant b of the mean and std rows, as
+    oracle/bf16ref.py writes them), content 2 alpha (V - F_c) from the unrounded content
+    value.  n_ps: whole-image feature counts per style layer (default: those of ``acts``)."""
     q = quant(prec)
     seeds = {}
     for k, i in enumerate(net.style):
         c, h, w = acts[i].shape
         n_p = h * w if n_ps is None else n_ps[k]
         d = grams_x[k] - g_t[k]
-        dt = q((2.0 * w_style[k] / n_p) * (d + d.T))
+        dt = (2.0 * w_style[k] / n_p) * (d + d.T)
+        b = None
+        if ms is not None:
+            r, b = bf16ref.ms_operands(grams_x[k], g_t[k], ms.means_x[k], ms.means_t[k], ms.w_mean[k],
+                                       ms.w_std[k], n_p)
+            dt = dt + np.diag(r)
+        dt = q(dt)
         seeds[i] = (dt @ acts[i].reshape(c, -1)).reshape(acts[i].shape)
+        if b is not None:
+            seeds[i] = seeds[i] + b[:, None, None]
     if net.content is not None and alpha != 0.0:
         seeds[net.content] = seeds.get(net.content, 0.0) + 2.0 * alpha * (raw_c - f_c)
     return seeds

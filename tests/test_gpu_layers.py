@@ -30,8 +30,9 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_common import (case, check_forward, cuda, fc_hwc, flat_grams, gpu_acts, layer_input, oracle_targets, quant,
-                        rel, seeds_on)
+from gpu_common import (case, check_forward, cuda, fc_hwc, flat_grams, gpu_acts, layer_input, mean_std,
+                        oracle_targets, quant, rel, seeds_on)
+from oracle.loss import channel_mean, std_from_stats
 from oracle import bf16ref
 from oracle.loss import gram
 from oracle.ops import conv3x3, relu
@@ -67,7 +68,7 @@ def ctx(kind, prec, with_content=True):
     return _ctx[key]
 
 
-def run_stages(name, prec, alpha=1.0, w_style=None, with_content=True):
+def run_stages(name, prec, alpha=1.0, w_style=None, with_content=True, msw=None):
     spec, T, m = CONFIGS[name]
     kind, H, W, Hs, Ws, sigma = spec
     k = case(*spec)
@@ -91,12 +92,27 @@ def run_stages(name, prec, alpha=1.0, w_style=None, with_content=True):
     acts = gpu_acts(nst, x_d, T, m, top)
     check_forward(net, acts, ws, bs, k["x"], prec, label)
 
-    # Step 1: Grams of x and energies
+    # Step 1: Grams of x (and channel means) and energies
     q = quant(prec)
-    energy, gx, _ = nst.loss_grad(x_d, gt_d, fc_d, w_style, alpha, T, m, flags=1)
+    ms, ms_gpu = mean_std(spec, msw), None
+    if ms is not None:
+        from paper_2212_13459_amd import MeanStdTerms
+        ms_gpu = MeanStdTerms(msw[0], msw[1], cuda(np.concatenate(ms.means_t), torch.float64))
+    energy, gx, _ = nst.loss_grad(x_d, gt_d, fc_d, w_style, alpha, T, m, flags=1, ms=ms_gpu)
     grams_x = [g.double().cpu().numpy() for g in nst.split_grams(gx)]
     gerr = [rel(G, gram(acts[i], acts[i].shape[1] * acts[i].shape[2])) for G, i in zip(grams_x, net.style)]
     e_style = [w_style[kk] * float(np.sum((grams_x[kk] - g_t[kk]) ** 2)) for kk in range(len(net.style))]
+    if ms is not None:
+        means_x = [v.double().cpu().numpy() for v in nst.split_means(ms_gpu.means_x)]
+        merr = [rel(mx, channel_mean(acts[i], acts[i].shape[1] * acts[i].shape[2]))
+                for mx, i in zip(means_x, net.style)]
+        print(f"  [{label} step1] channel means vs own features {['%.1e' % e for e in merr]}", flush=True)
+        assert max(merr) <= 1e-6, merr
+        ms = ms.with_x(means_x)
+        for kk in range(len(net.style)):
+            sx, st = std_from_stats(grams_x[kk], means_x[kk]), std_from_stats(g_t[kk], ms.means_t[kk])
+            e_style[kk] += msw[0][kk] * float(np.sum((means_x[kk] - ms.means_t[kk]) ** 2)) + \
+                msw[1][kk] * float(np.sum((sx - st) ** 2))
     es_err = [abs(a - b) / abs(b) for a, b in zip(energy[2:], e_style) if b != 0]
     raw_c, ec_err = None, 0.0
     if net.content is not None:
@@ -112,9 +128,9 @@ def run_stages(name, prec, alpha=1.0, w_style=None, with_content=True):
     assert ec_err <= (1e-6 if prec == "fp32" else 1e-5), ec_err
 
     # Step 2 with the Grams of x fixed: backward on the GPU's own activations
-    _, _, grad = nst.loss_grad(x_d, gt_d, fc_d, w_style, alpha, T, m, flags=2, grams_x=gx.clone())
+    _, _, grad = nst.loss_grad(x_d, gt_d, fc_d, w_style, alpha, T, m, flags=2, grams_x=gx.clone(), ms=ms_gpu)
     g_gpu = grad.double().cpu().numpy()
-    seeds = seeds_on(net, acts, raw_c, grams_x, g_t, f_c32, w_style, alpha, prec)
+    seeds = seeds_on(net, acts, raw_c, grams_x, g_t, f_c32, w_style, alpha, prec, ms=ms)
     g_ref = bf16ref.backward(net, acts, seeds, ws, q)
     derr = rel(g_gpu, g_ref)
     print(f"  [{label} step2] gradient vs reverse pass on own activations {derr:.2e}", flush=True)
@@ -144,3 +160,16 @@ def test_stages_texture_descriptor(prec):
     """Texture synthesis network (no content layer, alpha = 0; Sec. 6.2 uses the style
     term alone): same kernels, the top layer is conv5_1."""
     run_stages("ragged", prec, with_content=False)
+
+
+MSW5 = ((0.5, 1.0, 2.0, 4.0, 8.0), (2.0, 4.0, 8.0, 16.0, 32.0))
+MSW3 = ((0.5, 1.0, 2.0), (2.0, 4.0, 8.0))
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("name", ["tiny", "ragged"])
+def test_stages_mean_std(name, prec):
+    """The augmented style loss (Eq. 5): channel means of x against those of the GPU's own
+    features, the augmented energy terms, and the Step 2 gradient with the mean and std
+    rows of Table 1 on the GPU's own activations."""
+    run_stages(name, prec, msw=MSW3 if name == "tiny" else MSW5)

@@ -32,8 +32,8 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_common import (bf16ref_loss, case, cuda, fc_hwc, flat_grams, flip_corrected, oracle_loss, oracle_targets,
-                        rel, to_np)
+from gpu_common import (bf16ref_loss, case, cuda, fc_hwc, flat_grams, flip_corrected, oracle_loss,
+                        oracle_style_means, oracle_targets, rel, to_np)
 
 pytestmark = pytest.mark.gpu
 
@@ -62,27 +62,34 @@ def ctx(kind, prec, bias=0.0):
     return _ctx[key]
 
 
-def run_gpu(spec, prec, T, m, w_style, alpha, bias=0.0, oracle_inputs=True, flags=3):
+def run_gpu(spec, prec, T, m, w_style, alpha, bias=0.0, oracle_inputs=True, flags=3, msw=None):
     kind, H, W, Hs, Ws, sigma = spec
     k = case(kind, H, W, Hs, Ws, sigma, bias)
     nst = ctx(kind, prec, bias)
+    ms = None
     if oracle_inputs:
         g_t, f_c = oracle_targets(kind, H, W, Hs, Ws, sigma, bias)
         gt_d = cuda(flat_grams(g_t), torch.float64)
         fc_d = cuda(fc_hwc(f_c))
+        if msw is not None:
+            from paper_2212_13459_amd import MeanStdTerms
+            ms = MeanStdTerms(msw[0], msw[1], cuda(np.concatenate(oracle_style_means(*spec, bias)), torch.float64))
     else:
         gt_d = nst.style_grams(cuda(k["s"]), T, m)
         fc_d = nst.content_feats(cuda(k["c"]), T, m)
-    energy, gx, grad = nst.loss_grad(cuda(k["x"]), gt_d, fc_d, w_style, alpha, T, m, flags=flags)
+    energy, gx, grad = nst.loss_grad(cuda(k["x"]), gt_d, fc_d, w_style, alpha, T, m, flags=flags, ms=ms)
     torch.cuda.synchronize()
-    return energy, nst.split_grams(gx), grad
+    means = None if ms is None else nst.split_means(ms.means_x)
+    return energy, nst.split_grams(gx), grad, means
 
 
-def compare(spec, prec, T, m, w_style, alpha, gram_tol, grad_tol, e_tol, bias=0.0, label=""):
+def compare(spec, prec, T, m, w_style, alpha, gram_tol, grad_tol, e_tol, bias=0.0, label="", msw=None):
     kind, H, W, Hs, Ws, sigma = spec
-    terms, ograd = oracle_loss(kind, H, W, Hs, Ws, sigma, tuple(w_style), alpha, bias)
-    energy, grams, grad = run_gpu(spec, prec, T, m, w_style, alpha, bias)
+    terms, ograd = oracle_loss(kind, H, W, Hs, Ws, sigma, tuple(w_style), alpha, bias, msw)
+    energy, grams, grad, means = run_gpu(spec, prec, T, m, w_style, alpha, bias, msw=msw)
     gerr = [rel(to_np(g), go) for g, go in zip(grams, terms["grams"])]
+    if means is not None:
+        gerr += [rel(to_np(a), b) for a, b in zip(means, terms["means"])]
     derr = rel(to_np(grad), ograd)
     eerr = [abs(energy[0] - terms["E"]) / abs(terms["E"])]
     if alpha != 0:
@@ -93,7 +100,7 @@ def compare(spec, prec, T, m, w_style, alpha, gram_tol, grad_tol, e_tol, bias=0.
     print(f"[{label} {prec} {spec} T={T} m={m} alpha={alpha} w={w_style}] gram rel {['%.2e' % e for e in gerr]}"
           f" grad rel {derr:.2e} energy rel {['%.2e' % e for e in eerr]}", flush=True)
     if prec == "bf16":
-        bterms, bgrad = bf16ref_loss(kind, H, W, Hs, Ws, sigma, tuple(w_style), alpha, bias)
+        bterms, bgrad = bf16ref_loss(kind, H, W, Hs, Ws, sigma, tuple(w_style), alpha, bias, msw)
         ref_err = rel(bgrad, ograd)
         bg = [rel(to_np(g), go) for g, go in zip(grams, bterms["grams"])]
         be = [abs(energy[0] - bterms["E"]) / abs(bterms["E"])]
@@ -106,7 +113,8 @@ def compare(spec, prec, T, m, w_style, alpha, gram_tol, grad_tol, e_tol, bias=0.
     assert max(gerr) <= gram_tol, gerr
     assert max(eerr) <= e_tol, eerr
     if derr > grad_tol and prec == "fp32":
-        resid, flips = flip_corrected(kind, H, W, Hs, Ws, sigma, tuple(w_style), alpha, to_np(grad), bias)
+        resid, flips = flip_corrected(kind, H, W, Hs, Ws, sigma, tuple(w_style), alpha, to_np(grad), bias,
+                                      msw=msw)
         print(f"    flip-corrected grad rel {resid:.2e} after {len(flips)} near-tie flips, margins/rms "
               f"{['%.1e' % f[0] for f in flips[:12]]} kinds {sorted(set((f[1], f[2]) for f in flips))}", flush=True)
         derr = resid
@@ -140,6 +148,35 @@ def test_tiny_bf16(alpha, w):
 @pytest.mark.parametrize("alpha,w", [(1.0, W5), (0.0, W5)])
 def test_full_ragged_bf16(alpha, w):
     compare(RAGGED, "bf16", 96, 155, w, alpha, 2e-2, None, 3e-2, label="ragged")
+
+
+# -------------------------------------------------- augmented style loss (Eq. 5) ----
+
+MSW5 = ((0.5, 1.0, 2.0, 4.0, 8.0), (2.0, 4.0, 8.0, 16.0, 32.0))
+
+
+@pytest.mark.parametrize("alpha", [1.0, 0.0])
+def test_full_ragged_mean_std_fp32(alpha):
+    compare(RAGGED, "fp32", 96, 155, W5, alpha, 1e-5, 1e-4, 1e-5, label="ragged-ms", msw=MSW5)
+
+
+def test_full_ragged_mean_std_bf16():
+    compare(RAGGED, "bf16", 96, 155, W5, 1.0, 2e-2, None, 3e-2, label="ragged-ms", msw=MSW5)
+
+
+def test_style_stats_means():
+    """nst_style_stats: the Grams equal nst_style_grams bit for bit, the channel means
+    match the FP64 oracle (FP32 path)."""
+    kind, H, W, Hs, Ws, sigma = RAGGED
+    k = case(*RAGGED)
+    nst = ctx(kind, "fp32")
+    g1 = nst.style_grams(cuda(k["s"]), 64, 155)
+    g2, mu = nst.style_stats(cuda(k["s"]), 64, 155)
+    torch.cuda.synchronize()
+    assert torch.equal(g1, g2)
+    err = [rel(to_np(a), b) for a, b in zip(nst.split_means(mu), oracle_style_means(*RAGGED))]
+    print(f"[style means fp32] rel {['%.1e' % e for e in err]}", flush=True)
+    assert max(err) <= 1e-6
 
 
 # --------------------------------------------------------- targets and features ----
