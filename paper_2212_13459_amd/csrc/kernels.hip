@@ -890,9 +890,10 @@ __global__ __launch_bounds__(WM * WN * 64, SA ? (BN <= 64 ? 3 : 2) : 1) void k_c
   const int t = find_tile(g, patch);
   const int lb = patch - g.pfx[t];
   const int h = g.h[t], w = g.w[t];
-  // output region: the window, or for the image-gradient stitch the tile's owned pixels
-  const int oy = EPI == EPI_STITCH ? g.a0[t] : 0, ox = EPI == EPI_STITCH ? g.a2[t] : 0;
-  const int ey = EPI == EPI_STITCH ? g.a1[t] : h, ex = EPI == EPI_STITCH ? g.a3[t] : w;
+  // output region: the window (forward), or the region a0..a3 (the image-gradient stitch:
+  // the tile's owned pixels; a data gradient: what the block's gradient depends on)
+  const int oy = EPI != EPI_FWD ? g.a0[t] : 0, ox = EPI != EPI_FWD ? g.a2[t] : 0;
+  const int ey = EPI != EPI_FWD ? g.a1[t] : h, ex = EPI != EPI_FWD ? g.a3[t] : w;
   const int nbx = (ex - ox + PW - 1) / PW;
   const int y0 = oy + (lb / nbx) * PH, x0 = ox + (lb % nbx) * PW;
   const int n0 = (seq % nbn) * BN;
@@ -1380,11 +1381,13 @@ __global__ __launch_bounds__(256) void k_pool_bwd(const T *dp, long long dp_ss, 
   const int t = find_tile(g, blockIdx.x);
   const int item = (blockIdx.x - g.pfx[t]) * 256 + threadIdx.x;
   const int h = g.h[t], w = g.w[t];
-  const int hw2 = (h + 1) / 2, ww2 = (w + 1) / 2;
+  // pooling windows of the region a0..a1 x a2..a3 (pooled coordinates; a window past the
+  // floor-mode size covers the dropped last row / column, which gets 0)
+  const int rw2 = g.a3[t] - g.a2[t];
   constexpr int N = Vec<T>::N;
   const int nv = C / N;
-  if (item >= hw2 * ww2 * nv) return;
-  const int v = item % nv, p = item / nv, wy = p / ww2, wx = p - wy * ww2;
+  if (item >= (g.a1[t] - g.a0[t]) * rw2 * nv) return;
+  const int v = item % nv, p = item / nv, wy = g.a0[t] + p / rw2, wx = g.a2[t] + p % rw2;
   const long long slot = g.slot[t];
   const bool full = (2 * wy + 1 < h) && (2 * wx + 1 < w);
   Vec<T> av[4], dv;

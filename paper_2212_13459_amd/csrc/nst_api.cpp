@@ -4,6 +4,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
@@ -34,6 +35,8 @@ struct Geom {
   int content;                  // -1 if none
   int top;                      // deepest conv the energy uses
   int min_halo;
+  int rf_a[NST_MAX_CONV], rf_b[NST_MAX_CONV];   // feature q of conv i sees input rows [s q - a, s q + b]
+  int step1_halo;               // margin that makes the owned style / content features exact
 };
 
 int floor_div(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
@@ -77,6 +80,8 @@ int make_geom(const nst_net_desc *d, Geom *g) {
     g->stride[i] = s;
     a += s;
     b += s;
+    g->rf_a[i] = a;
+    g->rf_b[i] = b;
     mh = std::max(mh, a + b);
     if (g->pool[i]) {
       b += s;
@@ -85,6 +90,13 @@ int make_geom(const nst_net_desc *d, Geom *g) {
   }
   g->S = g->stride[top];
   g->min_halo = mh;
+  // Step 1 only needs the owned features of the style and content layers: a feature whose
+  // anchor s q lies in [b0, b1) sees [b0 - a, b1 - 1 + b], inside a window of margin max(a, b)
+  g->step1_halo = 0;
+  for (int k = 0; k < g->n_style; ++k)
+    g->step1_halo = std::max(g->step1_halo, std::max(g->rf_a[g->style[k]], g->rf_b[g->style[k]]));
+  if (g->content >= 0)
+    g->step1_halo = std::max(g->step1_halo, std::max(g->rf_a[g->content], g->rf_b[g->content]));
   return NST_OK;
 }
 
@@ -542,7 +554,8 @@ struct Runner {
   const Geom &g;
   Layout L;
   bool retain = false;          // every tile has its own slot (activations stay resident)
-  std::vector<nst_tile> tiles;
+  std::vector<nst_tile> tiles;  // the plan the calls' windows come from
+  int m = 0;                    // the caller's margin (the layout is sized for its plan)
   char *ws;
   hipStream_t s;
   int H, W;
@@ -576,7 +589,7 @@ struct Runner {
   hipError_t conv(int in_mode, int epi, const ConvArgs &a, const Batch &b) {
     double px = 0;
     for (int k = 0; k < b.n; ++k)
-      px += epi == EPI_STITCH ? (double)(b.a1[k] - b.a0[k]) * (b.a3[k] - b.a2[k]) : (double)b.h[k] * b.w[k];
+      px += epi != EPI_FWD ? (double)(b.a1[k] - b.a0[k]) * (b.a3[k] - b.a2[k]) : (double)b.h[k] * b.w[k];
     const double es = (double)L.es;
     double mac, in_b;
     if (in_mode == IN_IMAGE) {
@@ -630,12 +643,17 @@ struct Runner {
     const int pw = conv_block_cols(c->prec, in_mode, epi, cout);
     b.pfx[0] = 0;
     for (int k = 0; k < b.n; ++k) {
-      // the image-gradient stitch covers only the tile's owned pixels
-      const int rh = epi == EPI_STITCH ? b.a1[k] - b.a0[k] : b.h[k];
-      const int rw = epi == EPI_STITCH ? b.a3[k] - b.a2[k] : b.w[k];
-      b.pfx[k + 1] = b.pfx[k] + ((rh + ph - 1) / ph) * ((rw + pw - 1) / pw);
+      // backward convolutions cover the region a0..a3 (the image-gradient stitch: the
+      // tile's owned pixels; the data gradients: the part of the window the block's
+      // gradient depends on), forward ones the whole window
+      const int rh = epi != EPI_FWD ? b.a1[k] - b.a0[k] : b.h[k];
+      const int rw = epi != EPI_FWD ? b.a3[k] - b.a2[k] : b.w[k];
+      b.pfx[k + 1] = b.pfx[k] + ((std::max(rh, 0) + ph - 1) / ph) * ((std::max(rw, 0) + pw - 1) / pw);
     }
   }
+  // Plan with a margin of its own (same blocks, windows no larger than the layout's).
+  void replan(int margin) { build_plan(g, H, W, T, std::min(m, margin), tiles); }
+  int T = 0;
   void items_pfx(Batch &b, const std::vector<long long> &items, int per_block) const {
     b.pfx[0] = 0;
     for (int k = 0; k < b.n; ++k)
@@ -739,6 +757,48 @@ struct Runner {
     const int vec = (int)(16 / es);
     char *cur = slot_base(L.s_d0), *oth = slot_base(L.s_d1);
     const int top = g.top;
+    // Needed regions (window-local rows r0..r1, columns c0..c1 at conv i's resolution) of
+    // dE/dZ_i: the block's image gradient reads dZ_0 on the block +- 1; dZ_{i-1} on R
+    // comes from the data gradient of conv i on R (through the pool: rows r0 / 2 ..
+    // (r1 + 1) / 2), which reads dZ_i one pixel further out.  Everything the block's
+    // gradient depends on is computed exactly as over the whole window.
+    std::vector<std::array<int, 4>> reg((size_t)n * (top + 1));
+    for (int k = 0; k < n; ++k) {
+      const nst_tile &t = tiles[first + k];
+      int r0 = t.by0 - t.ey0 - 1, r1 = t.by1 - t.ey0 + 1, c0 = t.bx0 - t.ex0 - 1, c1 = t.bx1 - t.ex0 + 1;
+      for (int i = 0; i <= top; ++i) {
+        if (i > 0) {
+          if (g.pool[i - 1]) {
+            r0 = (r0 >> 1) - 1;
+            r1 = ((r1 + 1) >> 1) + 1;
+            c0 = (c0 >> 1) - 1;
+            c1 = ((c1 + 1) >> 1) + 1;
+          } else {
+            --r0, ++r1, --c0, ++c1;
+          }
+        }
+        r0 = std::max(r0, 0), r1 = std::min(r1, lh(t, i));
+        c0 = std::max(c0, 0), c1 = std::min(c1, lw(t, i));
+        reg[(size_t)k * (top + 1) + i] = {r0, r1, c0, c1};
+      }
+    }
+    // output region of conv i's data gradient: R_{i-1}, or its pooled rows when a pool
+    // follows conv i - 1 (pool = true: the pooled region up to the ceiling of the
+    // pre-pool rows, for the pool backward; false: the pooled rows that exist)
+    auto out_region = [&](Batch &b, int i, bool pool_bwd) {
+      for (int k = 0; k < n; ++k) {
+        const nst_tile &t = tiles[first + k];
+        const std::array<int, 4> &r = reg[(size_t)k * (top + 1) + i - 1];
+        if (!g.pool[i - 1]) {
+          b.a0[k] = r[0], b.a1[k] = r[1], b.a2[k] = r[2], b.a3[k] = r[3];
+        } else {
+          const int hh = pool_bwd ? (lh(t, i - 1) + 1) / 2 : lh(t, i);
+          const int ww = pool_bwd ? (lw(t, i - 1) + 1) / 2 : lw(t, i);
+          b.a0[k] = r[0] >> 1, b.a1[k] = std::min((r[1] + 1) >> 1, hh);
+          b.a2[k] = r[2] >> 1, b.a3[k] = std::min((r[3] + 1) >> 1, ww);
+        }
+      }
+    };
     auto fill_seeds = [&](ConvArgs &a, int j) {
       // seeds and mask of conv j's post-ReLU output (Table 1 rows; ReLU'(0) = 0)
       a.mask = slot_base(L.s_act[j]);
@@ -759,6 +819,7 @@ struct Runner {
     };
     {
       Batch b = base_batch(first, n, top);
+      for (int k = 0; k < n; ++k) b.a0[k] = 0, b.a1[k] = b.h[k], b.a2[k] = 0, b.a3[k] = b.w[k];
       ConvArgs a;
       std::memset(&a, 0, sizeof(a));
       fill_seeds(a, top);
@@ -770,7 +831,8 @@ struct Runner {
       HIPCHK(conv(IN_NONE, EPI_BWD, a, b));
     }
     for (int i = top; i >= 1; --i) {
-      Batch b = base_batch(first, n, i);
+      Batch b = base_batch(first, n, i);   // conv i's window (its output: dA_{i-1} or the pooled dP)
+      out_region(b, i, false);
       ConvArgs a;
       std::memset(&a, 0, sizeof(a));
       a.in = cur;
@@ -787,14 +849,15 @@ struct Runner {
       if (g.pool[i - 1]) {
         // oth holds dE/d(pool output); route it back and apply seeds + mask
         Batch bp = base_batch(first, n, i - 1);
+        out_region(bp, i, true);
         std::vector<long long> items(n);
         const int C = g.cout[i - 1];
         for (int t = 0; t < n; ++t)
-          items[t] = (long long)((bp.h[t] + 1) / 2) * ((bp.w[t] + 1) / 2) * (C / vec);
+          items[t] = (long long)std::max(bp.a1[t] - bp.a0[t], 0) * std::max(bp.a3[t] - bp.a2[t], 0) * (C / vec);
         items_pfx(bp, items, 256);
         const bool cont = (i - 1) == g.content && use_content;
-        double px = 0;
-        for (int t = 0; t < n; ++t) px += (double)bp.h[t] * bp.w[t];
+        double px = 0;   // pre-pool pixels of the region
+        for (int t = 0; t < n; ++t) px += 4.0 * std::max(bp.a1[t] - bp.a0[t], 0) * std::max(bp.a3[t] - bp.a2[t], 0);
         HIPCHK(prof(c->prec == 1 ? "void nst::k_pool_bwd<__bf16>(__bf16 const*, long long, __bf16 const*, long long, float const*, long long, float, __bf16*, long long, int, nst::Batch)"
                                  : "void nst::k_pool_bwd<float>(float const*, long long, float const*, long long, float const*, long long, float, float*, long long, int, nst::Batch)",
                     0.0, 2.25 * px * C * es + (cont ? 4.0 * px * C : 0.0), [&] {
@@ -841,6 +904,8 @@ int setup(Runner &R, nst_ctx *ctx, int H, int W, int T, int m, void *ws, size_t 
   if (!ws) return NST_EINVAL;
   R.H = H;
   R.W = W;
+  R.T = T;
+  R.m = m;
   R.ws = (char *)ws;
   R.s = (hipStream_t)stream;
   build_plan(ctx->g, H, W, T, m, R.tiles);
@@ -874,10 +939,30 @@ int setup(Runner &R, nst_ctx *ctx, int H, int W, int T, int m, void *ws, size_t 
   return NST_OK;
 }
 
+// Restores the caller's plan when a pass that used a plan of its own returns.
+struct PlanScope {
+  Runner &R;
+  std::vector<nst_tile> saved;
+  bool on = false;
+  explicit PlanScope(Runner &r) : R(r) {}
+  void use(int margin) {
+    saved = R.tiles;
+    on = true;
+    R.replan(margin);
+  }
+  ~PlanScope() {
+    if (on) R.tiles.swap(saved);
+  }
+};
+
 // keep: also store full-resolution activations of pooled layers (for a Step 2 that
-// reuses this pass's activations); means: also sum the style features' channels
+// reuses this pass's activations; the windows are then Step 2's); means: also sum the
+// style features' channels.  Otherwise the windows have the Step 1 margin, which is all
+// the owned style and content features need.
 int step1(Runner &R, const float *x, const float *fc, bool keep, bool means) {
   const Geom &g = R.g;
+  PlanScope plan(R);
+  if (!keep) plan.use(g.step1_halo);
   HIPCHK(launch_fill_f64(R.gl<double>(R.L.g_gacc), (R.L.g_dt - R.L.g_gacc) / 8, 0.0, R.s));
   HIPCHK(launch_fill_f64(R.gl<double>(R.L.g_ec), 1, 0.0, R.s));
   if (means) HIPCHK(launch_fill_f64(R.gl<double>(R.L.g_csum), (size_t)R.L.total_c, 0.0, R.s));
@@ -979,6 +1064,7 @@ int nst_layer_feats(nst_ctx *ctx, const float *img, int H, int W, int T, int m, 
   Runner R(ctx);
   int st = setup(R, ctx, H, W, T, m, ws, ws_bytes, stream, 0);
   if (st != NST_OK) return st;
+  R.replan(std::max(ctx->g.rf_a[conv], ctx->g.rf_b[conv]));   // owned features of conv only
   const int nt = (int)R.tiles.size();
   const int vec = (int)(16 / R.L.es);
   for (int first = 0; first < nt; first += R.L.batch) {
