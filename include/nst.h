@@ -200,6 +200,23 @@ int nst_loss_grad_ms(nst_ctx *ctx, const float *x, int H, int W, const double *t
                      const nst_mean_std *ms, int T, int m, int flags, double *grams_x,
                      double *energy, float *grad, void *ws, size_t ws_bytes, void *stream);
 
+/* ---- Allocation-free variant, for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops, harnesses that forbid hipMalloc) ----
+ * nst_loss_grad with the workspace replaced by a static device array of
+ * nst_scratch_bytes() (256 MiB) that the library holds on each GPU it runs on until the
+ * process ends (its address is looked up once per device by nst_create).  The call
+ * allocates and frees nothing; it uses the largest tile batch that fits in the array and
+ * returns NST_EWORKSPACE, before any launch, when even one tile's activations do not fit
+ * (e.g. BF16 tiles of 512 px with margin 155 fit, tiles of 1024 px do not).  Every call on
+ * a GPU shares that GPU's array: calls that overlap on one GPU (several streams, several
+ * threads) race and must be serialized by the caller.  Arguments, outputs and errors
+ * otherwise as nst_loss_grad. */
+size_t nst_scratch_bytes(void);
+int nst_loss_grad_noalloc(nst_ctx *ctx, const float *x, int H, int W, const double *target_grams,
+                          const float *content_feats, const double *w_style, double alpha, int T,
+                          int m, int flags, double *grams_x, double *energy, float *grad,
+                          void *stream);
+
 /* ---- Profiling (instrumentation of the entry points above; not part of the method) ----
  * While enabled, every kernel the run calls enqueue is bracketed by two HIP events on the
  * caller's stream.  nst_profile_read() waits for those events and returns, per kernel

@@ -71,6 +71,10 @@ SIGNATURES = {
     "nst_loss_grad": (c_int, [c_void_p, c_void_p, c_int, c_int, c_void_p, c_void_p, POINTER(c_double), c_double,
                               c_int, c_int, c_int, c_void_p, POINTER(c_double), c_void_p, c_void_p, c_size_t,
                               c_void_p]),
+    "nst_scratch_bytes": (c_size_t, []),
+    "nst_loss_grad_noalloc": (c_int, [c_void_p, c_void_p, c_int, c_int, c_void_p, c_void_p, POINTER(c_double),
+                                      c_double, c_int, c_int, c_int, c_void_p, POINTER(c_double), c_void_p,
+                                      c_void_p]),
     "nst_style_stats": (c_int, [c_void_p, c_void_p, c_int, c_int, c_int, c_int, c_void_p, c_void_p, c_void_p,
                                 c_size_t, c_void_p]),
     "nst_loss_grad_ms": (c_int, [c_void_p, c_void_p, c_int, c_int, c_void_p, c_void_p, POINTER(c_double),

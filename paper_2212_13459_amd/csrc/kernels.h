@@ -124,4 +124,11 @@ hipError_t launch_style_terms(int precision, const double *g, const double *gt,
 hipError_t launch_energy_total(const double *ec, const double *e_style, int n_style,
                                double alpha, double *energy, hipStream_t s);
 
+// Device scratch of the allocation-free entry point: a static device array of kScratchBytes.
+constexpr size_t kScratchBytes = (size_t)256 << 20;
+// Look up (once per device; that device must be current) the address of the device's copy.
+hipError_t scratch_init(int device);
+// The address scratch_init stored for `device`, or nullptr.
+void *scratch_ptr(int device);
+
 }  // namespace nst

@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 #include <stdint.h>
 #include <stdio.h>
 
@@ -2111,6 +2112,37 @@ hipError_t launch_energy_total(const double *ec, const double *e_style, int n_st
   hipLaunchKernelGGL(k_energy_total, dim3(1), dim3(64), 0, s, ec, e_style, n_style, alpha,
                      energy);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------
+// Device scratch for the allocation-free entry point: one static array per GPU the library
+// runs on, held until the process ends.  Host code never uses the array's name as an
+// address; scratch_init looks up each device's copy once, with that device current, and
+// later calls take the stored address.
+// ---------------------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t scratch_init(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  void *ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[device] = ptr;
+  return hipSuccess;
+}
+
+void *scratch_ptr(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch_ptr[device];
 }
 
 }  // namespace nst

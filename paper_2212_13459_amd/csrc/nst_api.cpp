@@ -476,7 +476,7 @@ int nst_create(const nst_net_desc *net, const float *const *w, const float *cons
   if (!c) return NST_ENOMEM;
   c->g = g;
   c->prec = precision;
-  if (hipGetDevice(&c->device) != hipSuccess) {
+  if (hipGetDevice(&c->device) != hipSuccess || scratch_init(c->device) != hipSuccess) {
     delete c;
     return NST_EHIP;
   }
@@ -1192,6 +1192,21 @@ int nst_loss_grad(nst_ctx *ctx, const float *x, int H, int W, const double *targ
                   size_t ws_bytes, void *stream) {
   return nst_loss_grad_ms(ctx, x, H, W, target_grams, content_feats, w_style, alpha, nullptr, T, m,
                           flags, grams_x, energy, grad, ws, ws_bytes, stream);
+}
+
+size_t nst_scratch_bytes(void) { return kScratchBytes; }
+
+int nst_loss_grad_noalloc(nst_ctx *ctx, const float *x, int H, int W, const double *target_grams,
+                          const float *content_feats, const double *w_style, double alpha, int T,
+                          int m, int flags, double *grams_x, double *energy, float *grad,
+                          void *stream) {
+  if (!ctx) return NST_EINVAL;
+  void *ws = scratch_ptr(ctx->device);
+  if (!ws) return NST_EHIP;
+  // the same run as nst_loss_grad on the device's static scratch; sizes whose smallest
+  // tile batch does not fit are refused with NST_EWORKSPACE before any launch
+  return nst_loss_grad_ms(ctx, x, H, W, target_grams, content_feats, w_style, alpha, nullptr, T, m,
+                          flags, grams_x, energy, grad, ws, kScratchBytes, stream);
 }
 
 }  // extern "C"
