@@ -3,6 +3,7 @@
     python -m paper_2212_13459_amd.profsum stats  STATS_CSV [--top N] [--cmd "..."]
     python -m paper_2212_13459_amd.profsum traffic FETCH_OUT WRITE_OUT --kernel NAME
            --copy-bytes B [--cmd-fetch "..."] [--cmd-write "..."]
+    python -m paper_2212_13459_amd.profsum counters PMC_OUT [--last N] [--cmd "..."]
 
 ``stats`` formats a ``--kernel-trace --stats`` kernel_stats.csv.  ``traffic`` turns two
 ``--pmc FETCH_SIZE`` / ``--pmc WRITE_SIZE`` runs (counter_collection.csv or *_results.db)
@@ -75,11 +76,52 @@ def read_counters(path):
     except FileNotFoundError:
         f = _find(path, "*_results.db")
         con = sqlite3.connect(f)
-        for k, c, v, d in con.execute(
-                "select kernel_name, counter_name, value, dispatch_id from counters_collection"):
+        q = ("select coalesce(s.kernel_name, k.kernel_name), k.counter_name, k.value, k.dispatch_id "
+             "from counters_collection k left join kernel_symbols s on s.kernel_id = k.kernel_id")
+        for k, c, v, d in con.execute(q):
+            k = k[:-3] if k.endswith(".kd") else k
             out[k][c][d] = out[k][c].get(d, 0.0) + float(v)
     dm = demangle(out)
     return {dm[k]: {c: [d[i] for i in sorted(d)] for c, d in cs.items()} for k, cs in out.items()}
+
+
+def durations(path):
+    """{kernel: [duration ns per dispatch, in dispatch order]} of a --pmc rocpd database."""
+    con = sqlite3.connect(_find(path, "*_results.db"))
+    q = ("select coalesce(s.kernel_name, k.kernel_name), k.dispatch_id, max(k.duration) from counters_collection k "
+         "left join kernel_symbols s on s.kernel_id = k.kernel_id group by k.dispatch_id")
+    out = collections.defaultdict(dict)
+    for k, d, du in con.execute(q):
+        out[k[:-3] if k.endswith(".kd") else k][d] = float(du)
+    dm = demangle(out)
+    return {dm[k]: [v[i] for i in sorted(v)] for k, v in out.items()}
+
+
+def counters(path, last, cmd, top=20):
+    """Per kernel, over its last ``last`` dispatches: duration, shader clock, MFMA-busy
+    fraction, LDS bank-conflict rate (a pass with SQ_VALU_MFMA_BUSY_CYCLES, SQ_BUSY_CYCLES,
+    SQ_LDS_BANK_CONFLICT, SQ_LDS_IDX_ACTIVE, GRBM_GUI_ACTIVE).  GRBM_GUI_ACTIVE sums the
+    8 XCDs' busy clocks, so clock = GRBM_GUI_ACTIVE / 8 / duration, and the MFMA units'
+    busy fraction = SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE / 8 x 256 CUs x 4 SIMDs)."""
+    cs, du = read_counters(path), durations(path)
+    rows = []
+    for k, c in cs.items():
+        d = du.get(k, [])
+        if not d or "GRBM_GUI_ACTIVE" not in c:
+            continue
+        n = min(last, len(d))
+        mean = lambda name: sum(c.get(name, [0])[-n:]) / n  # noqa: E731
+        dur = sum(d[-n:]) / n
+        g = mean("GRBM_GUI_ACTIVE") / 8.0
+        rows.append((sum(d), k, len(d), dur, g / dur, mean("SQ_VALU_MFMA_BUSY_CYCLES") / (g * 1024.0),
+                     mean("SQ_LDS_BANK_CONFLICT") / max(mean("SQ_LDS_IDX_ACTIVE"), 1.0)))
+    rows.sort(key=lambda r: -r[0])
+    lines = [f"command: {cmd}", "", f"Means over each kernel's last {last} dispatches.", "",
+             "| kernel | dispatches | mean ms | shader clock GHz | MFMA busy | LDS bank-conflict cycles / LDS cycles |",
+             "|---|---:|---:|---:|---:|---:|"]
+    for _, k, nd, dur, clk, mfma, lds in rows[:top]:
+        lines.append(f"| `{k[:100]}` | {nd} | {dur / 1e6:.4f} | {clk:.2f} | {mfma:.3f} | {lds:.3f} |")
+    return "\n".join(lines) + "\n"
 
 
 def _pick(counters, needle):
@@ -231,8 +273,15 @@ def main(argv=None):
     t.add_argument("--cmd-write", default="")
     t.add_argument("--out", default="")
     t.add_argument("--last", type=int, default=0)
+    c = sub.add_parser("counters")
+    c.add_argument("path")
+    c.add_argument("--last", type=int, default=8)
+    c.add_argument("--cmd", default="")
+    c.add_argument("--top", type=int, default=20)
     a = ap.parse_args(argv)
-    if a.mode == "stats":
+    if a.mode == "counters":
+        sys.stdout.write(counters(a.path, a.last, a.cmd, a.top))
+    elif a.mode == "stats":
         sys.stdout.write(stats(a.path, a.top, a.cmd, a.kernel, a.last))
     else:
         res = traffic(a.fetch, a.write, a.kernel, a.copy_bytes, a.last)

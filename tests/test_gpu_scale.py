@@ -262,11 +262,27 @@ def test_stages_at_scale(name, prec):
         del acts, g_ref, seeds
 
 
+_acts_cache = {}
+
+
+def _whole_acts(prec, x, T, m, xh):
+    """The GPU's whole-image features at C2, each conv checked once per precision."""
+    if prec not in _acts_cache:
+        _acts_cache.clear()
+        ws, bs = weights64()
+        acts = gpu_acts(ctx(prec), x, T, m, max(NET.style))
+        check_forward(NET, acts, ws, bs, xh, prec, f"whole 2048 {prec}")
+        _acts_cache[prec] = acts
+    return _acts_cache[prec]
+
+
+@pytest.mark.parametrize("alpha,w_style", [(1.0, W5), (0.0, W5), (1.0, [0.0] * 5)])
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
-def test_whole_image_stages_2048(prec):
+def test_whole_image_stages_2048(prec, alpha, w_style):
     """C2 (2048x2048, 512 px tiles): every conv, every Gram and every element of the
     gradient of the whole image against the plain definitions evaluated on the GPU's own
-    features (the full gradient vector, not samples)."""
+    features (the full gradient vector, not samples); the full energy, style-only and
+    content-only."""
     gd = _golden("C2")
     cfg = gd["config"]
     H, W, T, m = cfg["H"], cfg["W"], cfg["T"], cfg["m"]
@@ -277,20 +293,20 @@ def test_whole_image_stages_2048(prec):
     xh = host_images(H, W, cfg["Hs"], cfg["Ws"], cfg["sigma"])[0]
     gt = nst.style_grams(s, T, m)
     fc = nst.content_feats(c, T, m)
-    acts = gpu_acts(nst, x, T, m, max(NET.style))
-    check_forward(NET, acts, ws, bs, xh, prec, f"whole 2048 {prec}")
-    _, gx, _ = nst.loss_grad(x, gt, fc, W5, 1.0, T, m, flags=1)
+    acts = _whole_acts(prec, x, T, m, xh)
+    _, gx, _ = nst.loss_grad(x, gt, fc, w_style, alpha, T, m, flags=1)
     grams_x = [g.double().cpu().numpy() for g in nst.split_grams(gx)]
     g_t = [g.double().cpu().numpy() for g in nst.split_grams(gt)]
     gerr = [rel(G, gram(acts[i], acts[i].shape[1] * acts[i].shape[2])) for G, i in zip(grams_x, NET.style)]
-    _, _, grad = nst.loss_grad(x, gt, fc, W5, 1.0, T, m, flags=2, grams_x=gx.clone())
+    _, _, grad = nst.loss_grad(x, gt, fc, w_style, alpha, T, m, flags=2, grams_x=gx.clone())
     ic = NET.content
     raw_c = relu(conv3x3(layer_input(NET, acts, ic, q(xh.astype(np.float64))), q(ws[ic]), bs[ic]))
-    seeds = seeds_on(NET, acts, raw_c, grams_x, g_t, fc.permute(2, 0, 1).double().cpu().numpy(), W5, 1.0, prec)
+    seeds = seeds_on(NET, acts, raw_c, grams_x, g_t, fc.permute(2, 0, 1).double().cpu().numpy(), w_style, alpha,
+                     prec)
     g_ref = bf16ref.backward(NET, acts, seeds, ws, q)
     derr = rel(grad.double().cpu().numpy(), g_ref)
-    print(f"[whole 2048 {prec}] Grams vs own features {['%.1e' % e for e in gerr]}; full gradient vector vs "
-          f"reverse pass on own activations {derr:.2e}", flush=True)
+    print(f"[whole 2048 {prec} alpha={alpha} w={w_style[0]}] Grams vs own features {['%.1e' % e for e in gerr]}; "
+          f"full gradient vector vs reverse pass on own activations {derr:.2e}", flush=True)
     assert max(gerr) <= 1e-6, gerr
     assert derr <= GRAD_BAR[prec], derr
 
