@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define NST_ABI_VERSION 1
+#define NST_ABI_VERSION 2
 #define NST_MAX_CONV 16
 #define NST_MAX_STYLE 8
 
@@ -75,8 +75,10 @@ enum {
 };
 
 /* A VGG-style feature network: n_conv 3x3 convs (zero padding 1, stride 1), each followed
- * by ReLU, some followed by a 2x2 stride-2 floor-mode max pool.  Style layers and the
- * content layer name convs whose post-ReLU (pre-pool) output is used.  Supported shapes:
+ * by ReLU, some followed by a 2x2 stride-2 floor-mode pool (max, or average where
+ * pool_avg says so: the average-pooling variant of the network used for texture synthesis
+ * by the work the paper builds on).  Style layers and the content layer name convs whose
+ * post-ReLU (pre-pool) output is used.  Supported shapes:
  * c_in[0] == 3; c_in[i] == c_out[i-1]; c_out[i] == 64 or a multiple of 128; no style layer
  * is followed by a pool below the deepest used conv; convs after the deepest style/content
  * layer are ignored. */
@@ -88,6 +90,8 @@ typedef struct {
   int n_style;
   int style_conv[NST_MAX_STYLE];  /* increasing conv indices                              */
   int content_conv;               /* conv index, or -1 (no content term)                  */
+  unsigned pool_avg;              /* bit i set: the pool after conv i averages (bits outside
+                                     pool_after are an error)                            */
 } nst_net_desc;
 
 /* One block of the plan.  Image-pixel coordinates, half-open. */

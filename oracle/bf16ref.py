@@ -6,7 +6,7 @@ each point where a BF16 evaluation stores it, namely
 
 * the operands of the convolutions: the network weights and the input image;
 * every post-ReLU activation A_i.  The Gram matrices, the max pooling and the ReLU masks
-  of the backward pass read these stored values;
+  of the backward pass read these stored values; an average pool's output;
 * the residual operand (2 w_l / n_p)(D_l + D_l^T) of each style layer (Table 1, Gram row),
   with the augmented loss (Eq. 5) plus diag(r), r = (2 w'' / n_p)(std - std_ref) / std, the
   part of the std row that multiplies V; the per-channel rest of the mean and std rows,
@@ -30,7 +30,7 @@ import numpy as np
 
 from .loss import channel_mean, energy_terms, gram, last_needed, std_from_stats
 from .net import NetSpec
-from .ops import conv3x3, conv3x3_adjoint, maxpool2, maxpool2_backward, relu
+from .ops import conv3x3, conv3x3_adjoint, pool2, pool2_backward, relu
 
 
 def round_bf16(a) -> np.ndarray:
@@ -59,7 +59,11 @@ def forward(net: NetSpec, x, ws, bs, q=round_bf16, upto: int | None = None):
         ai = q(r)
         stored.append(ai)
         raw.append(r)
-        a = maxpool2(ai) if i in net.pool_after else ai
+        # a max pool picks a stored value; an average pool's mean is stored rounded
+        if i in net.pool_after:
+            a = q(pool2(ai, True)) if net.avg_pool else pool2(ai, False)
+        else:
+            a = ai
     return stored, raw
 
 
@@ -74,7 +78,7 @@ def backward(net: NetSpec, acts, seeds: dict, ws, q=round_bf16) -> np.ndarray:
         dz = q(np.where(acts[i] > 0.0, da, 0.0))
         dx = conv3x3_adjoint(dz, q(np.asarray(ws[i], np.float64)))
         if i > 0 and (i - 1) in net.pool_after:
-            g = maxpool2_backward(q(dx), acts[i - 1])
+            g = pool2_backward(q(dx), acts[i - 1], net.avg_pool)
         else:
             g = dx
     return g

@@ -25,7 +25,7 @@ import numpy as np
 
 from .loss import last_needed
 from .net import NetSpec, receptive_fields
-from .ops import conv3x3, conv3x3_adjoint, maxpool2_backward
+from .ops import avgpool2, conv3x3, conv3x3_adjoint, pool2_backward
 
 _ORDER = ((0, 0), (0, 1), (1, 0), (1, 1))
 
@@ -41,7 +41,9 @@ def fragile_units(net: NetSpec, acts, ws, bs, x, delta: float):
         for c, y, xx in np.argwhere(m < delta):
             out.append((float(m[c, y, xx]), "relu", i, int(c), int(y), int(xx)))
         act = acts[i]
-        if i in net.pool_after and i < last_needed(net):
+        if i in net.pool_after and i < last_needed(net) and net.avg_pool:
+            a = avgpool2(act)            # an average pool takes no decision
+        elif i in net.pool_after and i < last_needed(net):
             c_, h, w = act.shape
             h2, w2 = h // 2, w // 2
             v = np.stack([act[:, dy:2 * h2:2, dx:2 * w2:2] for dy, dx in _ORDER], -1)
@@ -79,7 +81,7 @@ def _backward_from(net, acts_c, i, dz, ws):
         dx = conv3x3_adjoint(dz, ws[j])
         if j == 0:
             return dx
-        da = maxpool2_backward(dx, acts_c[j - 1]) if (j - 1) in net.pool_after else dx
+        da = pool2_backward(dx, acts_c[j - 1], net.avg_pool) if (j - 1) in net.pool_after else dx
         dz = np.where(acts_c[j - 1] > 0.0, da, 0.0)
 
 
@@ -99,7 +101,7 @@ def flip_effect(net: NetSpec, record, ws, unit, shape):
     ly, lx = qy0 - Y0 // s, qx0 - X0 // s
     A = acts_c[i]
     dz = np.zeros_like(A)
-    if kind == "relu" and i in net.pool_after and ("dP", i) in record and \
+    if kind == "relu" and i in net.pool_after and not net.avg_pool and ("dP", i) in record and \
             qy // 2 < record[("dP", i)].shape[1] and qx // 2 < record[("dP", i)].shape[2]:
         # the unit feeds a max pool: flipping it can also move that window's maximum
         # (e.g. a unit that turns positive in an all-zero window takes the pooled gradient)

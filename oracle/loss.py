@@ -11,7 +11,7 @@ Definitions followed (Sec. 3.1, Sec. 4.2):
   Gram row written without assuming symmetry, dE/dV = (2 w / n_p) V (D + D^T)
   with D = G - G_ref, which equals the printed (4 w / n_p) V D when D is symmetric.
 * backward: reverse layer loop with ReLU'(0) = 0, max-pool routing to the
-  first maximum, conv adjoint.
+  first maximum (average pools: a quarter to each input), conv adjoint.
 
 Augmented style loss (Sec. 3.2, Eq. 5; Table 1 rows 3-4; Algorithm 1 Step 1):
 
@@ -32,7 +32,7 @@ from __future__ import annotations
 import numpy as np
 
 from .net import NetSpec
-from .ops import conv3x3, conv3x3_adjoint, maxpool2, maxpool2_backward, relu
+from .ops import conv3x3, conv3x3_adjoint, pool2, pool2_backward, relu
 
 
 def last_needed(net: NetSpec) -> int:
@@ -49,7 +49,7 @@ def forward(net: NetSpec, x: np.ndarray, ws, bs, upto: int | None = None):
         z = conv3x3(a, ws[i], bs[i])
         ai = relu(z)
         acts.append(ai)
-        a = maxpool2(ai) if i in net.pool_after else ai
+        a = pool2(ai, net.avg_pool) if i in net.pool_after else ai
     return acts
 
 
@@ -172,7 +172,7 @@ def backward(net: NetSpec, acts, seeds: dict, ws, record: dict | None = None) ->
         if i > 0 and (i - 1) in net.pool_after:
             if record is not None:
                 record[("dP", i - 1)] = dx
-            g = maxpool2_backward(dx, acts[i - 1])
+            g = pool2_backward(dx, acts[i - 1], net.avg_pool)
         else:
             g = dx
     return g

@@ -25,6 +25,7 @@ class NetSpec:
     style: tuple                      # conv indices whose ReLU output is a style layer
     content: int | None               # conv index of the content layer (None: texture)
     names: tuple = field(default=())
+    avg_pool: bool = False            # 2x2/2 average pools instead of max pools
 
     @property
     def n_conv(self) -> int:
@@ -44,17 +45,17 @@ class NetSpec:
         return self.strides()[-1]
 
 
-def vgg19(style_weights=None, content=True) -> NetSpec:
+def vgg19(style_weights=None, content=True, avg_pool=False) -> NetSpec:
     return NetSpec(convs=tuple(VGG19_CONVS), pool_after=frozenset({1, 3, 7, 11}),
                    style=(0, 2, 4, 8, 12), content=(9 if content else None),
-                   names=tuple(VGG19_NAMES))
+                   names=tuple(VGG19_NAMES), avg_pool=avg_pool)
 
 
-def vgg19_tiny(content=True) -> NetSpec:
+def vgg19_tiny(content=True, avg_pool=False) -> NetSpec:
     """Prefix conv1_1 .. conv3_1; style relu1_1, relu2_1, relu3_1; content relu2_2."""
     return NetSpec(convs=tuple(VGG19_CONVS[:5]), pool_after=frozenset({1, 3}),
                    style=(0, 2, 4), content=(3 if content else None),
-                   names=tuple(VGG19_NAMES[:5]))
+                   names=tuple(VGG19_NAMES[:5]), avg_pool=avg_pool)
 
 
 def receptive_fields(net: NetSpec):

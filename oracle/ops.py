@@ -9,7 +9,8 @@ It is written as nine shifted channel matmuls, one per filter tap.  The
 adjoint scatters each tap's transposed matmul back to the shifted position.
 Max pooling is 2x2, stride 2, floor mode; the backward routes the incoming
 gradient to the first maximum in the order (0,0), (0,1), (1,0), (1,1) and gives
-0 to rows/columns that floor mode drops.
+0 to rows/columns that floor mode drops.  Average pooling (the variant of the
+network with every max pool replaced by a 2x2 mean) has the same geometry.
 """
 from __future__ import annotations
 
@@ -58,6 +59,30 @@ def _pool_views(a: np.ndarray):
 
 def maxpool2(a: np.ndarray) -> np.ndarray:
     return _pool_views(a).max(axis=0)
+
+
+def avgpool2(a: np.ndarray) -> np.ndarray:
+    """2x2 stride-2 average pooling, floor mode."""
+    return _pool_views(a).mean(axis=0)
+
+
+def avgpool2_backward(dy: np.ndarray, a: np.ndarray) -> np.ndarray:
+    """Adjoint of ``avgpool2``: each output's gradient / 4 to its four inputs; rows and
+    columns that floor mode drops get 0."""
+    c, h, w = a.shape
+    h2, w2 = h // 2, w // 2
+    da = np.zeros((c, h, w), np.float64)
+    for dy_, dx_ in ((0, 0), (0, 1), (1, 0), (1, 1)):
+        da[:, dy_: 2 * h2: 2, dx_: 2 * w2: 2] = 0.25 * dy
+    return da
+
+
+def pool2(a: np.ndarray, avg: bool) -> np.ndarray:
+    return avgpool2(a) if avg else maxpool2(a)
+
+
+def pool2_backward(dy: np.ndarray, a: np.ndarray, avg: bool) -> np.ndarray:
+    return avgpool2_backward(dy, a) if avg else maxpool2_backward(dy, a)
 
 
 def maxpool2_backward(dy: np.ndarray, a: np.ndarray) -> np.ndarray:

@@ -20,7 +20,7 @@ STATUS = {0: "NST_OK", -1: "NST_EINVAL", -2: "NST_ESHAPE", -3: "NST_EHALO", -4: 
 class NetDesc(ctypes.Structure):
     _fields_ = [("n_conv", c_int), ("c_in", c_int * NST_MAX_CONV), ("c_out", c_int * NST_MAX_CONV),
                 ("pool_after", c_uint), ("n_style", c_int), ("style_conv", c_int * NST_MAX_STYLE),
-                ("content_conv", c_int)]
+                ("content_conv", c_int), ("pool_avg", c_uint)]
 
 
 class Tile(ctypes.Structure):

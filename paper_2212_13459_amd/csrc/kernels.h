@@ -42,8 +42,9 @@ struct ConvArgs {
   // output (EPI_FWD: may be null when only the pooled output is wanted)
   void *out;
   long long out_ss;
-  void *pool;                  // EPI_FWD: optional 2x2 max-pooled output (floor mode), NHWC
+  void *pool;                  // EPI_FWD: optional 2x2 pooled output (floor mode), NHWC
   long long pool_ss;
+  int pool_avg;                // that pool averages the four stored values (else: first maximum)
   int cout;                    // real output channels
   int cout_pad;                // padded N of the packed operands
   const float *bias;           // EPI_FWD: bias; EPI_BWD (optional): per-channel constant added
@@ -73,9 +74,10 @@ const char *conv_kernel_name(int precision, int in_mode, int epi, const ConvArgs
 int conv_block_rows(int precision, int in_mode, int epi, int cout); // patch rows
 int conv_block_cols(int precision, int in_mode, int epi, int cout); // patch columns
 
+// avg: the pool averaged (a quarter of dP to each input) instead of taking the first maximum
 hipError_t launch_pool_bwd(int precision, const void *dp, long long dp_ss, const void *act,
                            long long act_ss, const float *rc, long long rc_ss, float two_alpha,
-                           void *dz, long long dz_ss, int C, const Batch &g, hipStream_t s);
+                           void *dz, long long dz_ss, int C, bool avg, const Batch &g, hipStream_t s);
 hipError_t launch_gram(int precision, const void *act, long long act_ss, int C, const Batch &g,
                        float *part, long long part_ss, hipStream_t s);
 hipError_t launch_gram_tile_reduce(const float *part, long long part_ss, int C, const Batch &g,

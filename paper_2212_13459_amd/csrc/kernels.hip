@@ -104,8 +104,8 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a, Batch g) {
   const int t = find_tile(g, blockIdx.x);
   const int lb = blockIdx.x - g.pfx[t];
   const int h = g.h[t], w = g.w[t];
-  const int nbx = (w + PW - 1) / PW;
-  const int y0 = (lb / nbx) * PH, x0 = (lb % nbx) * PW;
+  const int nbx = (g.a3[t] - g.a2[t] + PW - 1) / PW;   // output region a0..a3
+  const int y0 = g.a0[t] + (lb / nbx) * PH, x0 = g.a2[t] + (lb % nbx) * PW;
   const int n0 = blockIdx.y * BN;
   const long long slot = g.slot[t];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -385,19 +385,30 @@ __device__ __forceinline__ void epi_bf16(f32x16 (&acc)[PH * 32 / (WM * 32)][BN /
     static_assert((PO * CPR) % NT == 0, "epilogue windows");
     bf16 *outb = a.out ? (bf16 *)a.out + slot * a.out_ss + n : nullptr;
     bf16 *poolb = a.pool ? (bf16 *)a.pool + slot * a.pool_ss + n : nullptr;
+    const bool pavg = a.pool_avg != 0;
     const int ho = h >> 1, wo = w >> 1;
 #pragma unroll
     for (int k = 0; k < NW; ++k) {
       const int q = ib + k * ISTEP;
       const int qy = q / PWO, qx = q % PWO;
       u16x8 best;
+      float sum[8];
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) {
         const int ly = 2 * qy + (kk >> 1), lx = 2 * qx + (kk & 1);
         const int py = y0 + ly, px = x0 + lx;
         const u16x8 u = *(const u16x8 *)(&sm[(ly * PW + lx) * RS + lc]);
         best = kk == 0 ? u : __builtin_elementwise_max(best, u);
+        if (pavg) {
+          // average pool: the mean of the four stored values, rounded once
+#pragma unroll
+          for (int e = 0; e < 8; ++e) sum[e] = (kk == 0 ? 0.f : sum[e]) + __builtin_bit_cast(float, (unsigned)u[e] << 16);
+        }
         if (outb && nok && py < h && px < w) *(u16x8 *)(outb + (long long)(py * w + px) * cout) = u;
+      }
+      if (pavg) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) best[e] = __builtin_bit_cast(unsigned short, (bf16)(0.25f * sum[e]));
       }
       const int oy = (y0 >> 1) + qy, ox = (x0 >> 1) + qx;   // patch origins are even
       if (poolb && nok && oy < ho && ox < wo) *(u16x8 *)(poolb + (long long)(oy * wo + ox) * cout) = best;
@@ -571,6 +582,7 @@ __device__ __forceinline__ void conv_epilogue(f32x16 (&acc)[PH * 32 / (WM * 32)]
     lds_barrier();
     if constexpr (EPI == EPI_FWD) {
       T *poolb = a.pool ? (T *)a.pool + slot * a.pool_ss + n : nullptr;
+      const bool pavg = a.pool_avg != 0;
       const int ho = h >> 1, wo = w >> 1;
 #pragma unroll
       for (int k = 0; k < NW; ++k) {
@@ -595,7 +607,9 @@ __device__ __forceinline__ void conv_epilogue(f32x16 (&acc)[PH * 32 / (WM * 32)]
           for (int e = 0; e < VEC; ++e) {
             o[e] = from_f<T>(v[e]);
             const float f = to_f(o[e]);
-            if (kk == 0 || f > bf[e]) {
+            if (pavg) {
+              bf[e] = (kk == 0 ? 0.f : bf[e]) + f;   // average pool: sum of the stored values
+            } else if (kk == 0 || f > bf[e]) {
               bf[e] = f;
               best[e] = o[e];
             }
@@ -615,6 +629,10 @@ __device__ __forceinline__ void conv_epilogue(f32x16 (&acc)[PH * 32 / (WM * 32)]
             }
             if (outb) *(TV *)(outb + po) = o;
           }
+        }
+        if (poolb && pavg) {
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) best[e] = from_f<T>(0.25f * bf[e]);
         }
         if (poolb) {
           const int q = ib + k * QSTEP;
@@ -891,10 +909,11 @@ __global__ __launch_bounds__(WM * WN * 64, SA ? (BN <= 64 ? 3 : 2) : 1) void k_c
   const int t = find_tile(g, patch);
   const int lb = patch - g.pfx[t];
   const int h = g.h[t], w = g.w[t];
-  // output region: the window (forward), or the region a0..a3 (the image-gradient stitch:
-  // the tile's owned pixels; a data gradient: what the block's gradient depends on)
-  const int oy = EPI != EPI_FWD ? g.a0[t] : 0, ox = EPI != EPI_FWD ? g.a2[t] : 0;
-  const int ey = EPI != EPI_FWD ? g.a1[t] : h, ex = EPI != EPI_FWD ? g.a3[t] : w;
+  // output region a0..a3 of the window (the image-gradient stitch: the tile's owned pixels;
+  // the other convolutions: what the pass needs; a pooled layer's region starts on even
+  // rows and columns)
+  const int oy = g.a0[t], ox = g.a2[t];
+  const int ey = g.a1[t], ex = g.a3[t];
   const int nbx = (ex - ox + PW - 1) / PW;
   const int y0 = oy + (lb / nbx) * PH, x0 = ox + (lb % nbx) * PW;
   const int n0 = (seq % nbn) * BN;
@@ -1084,8 +1103,8 @@ __device__ __forceinline__ void img_patch_load(float (&v)[4], const ConvArgs &a,
   const int t = find_tile(g, patch);
   const int lb = patch - g.pfx[t];
   const int h = g.h[t], w = g.w[t];
-  const int nbx = (w + PW - 1) / PW;
-  const int y0 = (lb / nbx) * PH, x0 = (lb % nbx) * PW;
+  const int nbx = (g.a3[t] - g.a2[t] + PW - 1) / PW;   // output region a0..a3
+  const int y0 = g.a0[t] + (lb / nbx) * PH, x0 = g.a2[t] + (lb % nbx) * PW;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int e = tid + i * 256;
@@ -1130,8 +1149,8 @@ __global__ __launch_bounds__(256, kImgBlocksPerCU<T>) void k_conv_img(ConvArgs a
     const int t = find_tile(g, patch);
     const int lb = patch - g.pfx[t];
     const int h = g.h[t], w = g.w[t];
-    const int nbx = (w + PW - 1) / PW;
-    const int y0 = (lb / nbx) * PH, x0 = (lb % nbx) * PW;
+    const int nbx = (g.a3[t] - g.a2[t] + PW - 1) / PW;   // output region a0..a3
+    const int y0 = g.a0[t] + (lb / nbx) * PH, x0 = g.a2[t] + (lb % nbx) * PW;
     const long long slot = g.slot[t];
     __syncthreads();   // the previous patch's epilogue is done with smem and ip
 #pragma unroll
@@ -1378,7 +1397,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_pool_bwd(const T *dp, long long dp_ss, const T *act,
                                                   long long act_ss, const float *rc,
                                                   long long rc_ss, float two_alpha, T *dz,
-                                                  long long dz_ss, int C, Batch g) {
+                                                  long long dz_ss, int C, bool avg, Batch g) {
   const int t = find_tile(g, blockIdx.x);
   const int item = (blockIdx.x - g.pfx[t]) * 256 + threadIdx.x;
   const int h = g.h[t], w = g.w[t];
@@ -1402,6 +1421,8 @@ __global__ __launch_bounds__(256) void k_pool_bwd(const T *dp, long long dp_ss, 
   }
   dv.u = make_uint4(0u, 0u, 0u, 0u);
   if (full) dv.u = *(const uint4 *)(dp + slot * dp_ss + ((long long)wy * (w / 2) + wx) * C + v * N);
+  // max pool: dP goes to the first maximum in window order; average pool: a quarter to
+  // each input (exact in BF16 and FP32)
   int arg[N];
 #pragma unroll
   for (int j = 0; j < N; ++j) {
@@ -1423,7 +1444,7 @@ __global__ __launch_bounds__(256) void k_pool_bwd(const T *dp, long long dp_ss, 
     Vec<T> o;
 #pragma unroll
     for (int j = 0; j < N; ++j) {
-      float val = (arg[j] == k) ? to_f(dv.e[j]) : 0.f;
+      float val = avg ? (full ? 0.25f * to_f(dv.e[j]) : 0.f) : ((arg[j] == k) ? to_f(dv.e[j]) : 0.f);
       if (rc) val += two_alpha * rc[slot * rc_ss + pix * C + v * N + j];
       if (!(to_f(av[k].e[j]) > 0.f)) val = 0.f;
       o.e[j] = from_f<T>(val);
@@ -1434,16 +1455,16 @@ __global__ __launch_bounds__(256) void k_pool_bwd(const T *dp, long long dp_ss, 
 
 hipError_t launch_pool_bwd(int precision, const void *dp, long long dp_ss, const void *act,
                            long long act_ss, const float *rc, long long rc_ss, float two_alpha,
-                           void *dz, long long dz_ss, int C, const Batch &g, hipStream_t s) {
+                           void *dz, long long dz_ss, int C, bool avg, const Batch &g, hipStream_t s) {
   const int nblk = g.pfx[g.n];
   if (nblk == 0) return hipSuccess;
   if (precision == 1)
     hipLaunchKernelGGL(k_pool_bwd<bf16>, dim3(nblk), dim3(256), 0, s, (const bf16 *)dp, dp_ss,
-                       (const bf16 *)act, act_ss, rc, rc_ss, two_alpha, (bf16 *)dz, dz_ss, C, g);
+                       (const bf16 *)act, act_ss, rc, rc_ss, two_alpha, (bf16 *)dz, dz_ss, C, avg, g);
   else
     hipLaunchKernelGGL(k_pool_bwd<float>, dim3(nblk), dim3(256), 0, s, (const float *)dp, dp_ss,
                        (const float *)act, act_ss, rc, rc_ss, two_alpha, (float *)dz, dz_ss, C,
-                       g);
+                       avg, g);
   return hipGetLastError();
 }
 

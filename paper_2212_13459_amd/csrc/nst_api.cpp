@@ -27,6 +27,7 @@ struct Geom {
   int n_conv;
   int cin[NST_MAX_CONV], cout[NST_MAX_CONV];
   bool pool[NST_MAX_CONV];      // pool after conv i (only for i < top)
+  bool pavg[NST_MAX_CONV];      // that pool averages
   int stride[NST_MAX_CONV];     // cumulative stride of conv i's output
   int S;                        // alignment of windows: stride of the deepest used conv
   int n_style;
@@ -49,6 +50,7 @@ int make_geom(const nst_net_desc *d, Geom *g) {
   std::memset(g, 0, sizeof(*g));
   if (d->n_conv < 1 || d->n_conv > NST_MAX_CONV) return NST_EINVAL;
   if (d->n_style < 0 || d->n_style > NST_MAX_STYLE) return NST_EINVAL;
+  if ((d->pool_avg & ~d->pool_after) != 0u) return NST_EINVAL;
   g->n_conv = d->n_conv;
   g->n_style = d->n_style;
   g->content = d->content_conv;
@@ -73,6 +75,7 @@ int make_geom(const nst_net_desc *d, Geom *g) {
     if (i > 0 && g->cin[i] != g->cout[i - 1]) return NST_EINVAL;
     if (!ok_channels(g->cout[i])) return NST_EINVAL;
     g->pool[i] = (i < top) && ((d->pool_after >> i) & 1u);
+    g->pavg[i] = g->pool[i] && ((d->pool_avg >> i) & 1u);
     if (g->pool[i] && g->style_of[i] >= 0) return NST_EINVAL;  // style layer before a pool
   }
   int s = 1, a = 0, b = 0, mh = 0;
@@ -549,6 +552,8 @@ namespace {
     if ((x) != hipSuccess) return NST_EHIP; \
   } while (0)
 
+using Reg = std::array<int, 4>;
+
 struct Runner {
   nst_ctx *c;
   const Geom &g;
@@ -589,7 +594,7 @@ struct Runner {
   hipError_t conv(int in_mode, int epi, const ConvArgs &a, const Batch &b) {
     double px = 0;
     for (int k = 0; k < b.n; ++k)
-      px += epi != EPI_FWD ? (double)(b.a1[k] - b.a0[k]) * (b.a3[k] - b.a2[k]) : (double)b.h[k] * b.w[k];
+      px += (double)std::max(b.a1[k] - b.a0[k], 0) * std::max(b.a3[k] - b.a2[k], 0);
     const double es = (double)L.es;
     double mac, in_b;
     if (in_mode == IN_IMAGE) {
@@ -643,11 +648,10 @@ struct Runner {
     const int pw = conv_block_cols(c->prec, in_mode, epi, cout);
     b.pfx[0] = 0;
     for (int k = 0; k < b.n; ++k) {
-      // backward convolutions cover the region a0..a3 (the image-gradient stitch: the
-      // tile's owned pixels; the data gradients: the part of the window the block's
-      // gradient depends on), forward ones the whole window
-      const int rh = epi != EPI_FWD ? b.a1[k] - b.a0[k] : b.h[k];
-      const int rw = epi != EPI_FWD ? b.a3[k] - b.a2[k] : b.w[k];
+      // every convolution covers its output region a0..a3 (the image-gradient stitch: the
+      // tile's owned pixels; the others: the part of the window the pass needs)
+      const int rh = b.a1[k] - b.a0[k];
+      const int rw = b.a3[k] - b.a2[k];
       b.pfx[k + 1] = b.pfx[k] + ((std::max(rh, 0) + ph - 1) / ph) * ((std::max(rw, 0) + pw - 1) / pw);
     }
   }
@@ -667,10 +671,17 @@ struct Runner {
 
   // keep_pooled: also store the full-resolution output of layers that are pooled (the
   // backward needs them; a forward-only pass needs just the pooled maps)
-  int forward(int first, int n, int upto, const float *img, const float *fc, bool keep_pooled) {
+  // regions: per tile k and conv i (index k (top + 1) + i), the output region to compute
+  // (window-local rows r0..r1, columns c0..c1 at conv i's resolution)
+  int forward(int first, int n, int upto, const float *img, const float *fc, bool keep_pooled,
+              const std::vector<Reg> &regions) {
     const size_t es = L.es;
     for (int i = 0; i <= upto; ++i) {
       Batch b = base_batch(first, n, i);
+      for (int k = 0; k < n; ++k) {
+        const Reg &r = regions[(size_t)k * (g.top + 1) + i];
+        b.a0[k] = r[0], b.a1[k] = r[1], b.a2[k] = r[2], b.a3[k] = r[3];
+      }
       ConvArgs a;
       std::memset(&a, 0, sizeof(a));
       int in_mode = IN_NHWC;
@@ -694,6 +705,7 @@ struct Runner {
       if (pooled) {
         a.pool = slot_base(L.s_pool[i]);
         a.pool_ss = ss(es);
+        a.pool_avg = g.pavg[i] ? 1 : 0;
         if (!keep_pooled) a.out = nullptr;
       }
       if (i == g.content && fc) {
@@ -706,6 +718,82 @@ struct Runner {
       HIPCHK(conv(in_mode, EPI_FWD, a, b));
     }
     return NST_OK;
+  }
+
+  // Needed regions of Step 2's data gradients: dE/dZ_i is needed on R_i.  The block's
+  // image gradient reads dZ_0 on the block +- 1; dZ_{i-1} on R comes from the data
+  // gradient of conv i on R (through a pool: rows r0 / 2 .. (r1 + 1) / 2), which reads
+  // dZ_i one pixel further out.  Clipped to the window.
+  void backward_regions(int first, int n, std::vector<Reg> &reg) const {
+    const int top = g.top;
+    reg.assign((size_t)n * (top + 1), Reg{0, 0, 0, 0});
+    for (int k = 0; k < n; ++k) {
+      const nst_tile &t = tiles[first + k];
+      int r0 = t.by0 - t.ey0 - 1, r1 = t.by1 - t.ey0 + 1, c0 = t.bx0 - t.ex0 - 1, c1 = t.bx1 - t.ex0 + 1;
+      for (int i = 0; i <= top; ++i) {
+        if (i > 0) {
+          if (g.pool[i - 1]) {
+            r0 = (r0 >> 1) - 1, r1 = ((r1 + 1) >> 1) + 1, c0 = (c0 >> 1) - 1, c1 = ((c1 + 1) >> 1) + 1;
+          } else {
+            --r0, ++r1, --c0, ++c1;
+          }
+        }
+        r0 = std::max(r0, 0), r1 = std::min(r1, lh(t, i));
+        c0 = std::max(c0, 0), c1 = std::min(c1, lw(t, i));
+        reg[(size_t)k * (top + 1) + i] = {r0, r1, c0, c1};
+      }
+    }
+  }
+
+  // Regions a forward pass must compute so that the activations of every conv i are
+  // exact on seed[i] (per tile and conv; an empty seed asks for nothing): conv i + 1 reads
+  // conv i's output one pixel around its own region, through a pool the two rows and
+  // columns under each pooled one.  Pooled layers start on even rows and columns (the
+  // pooling windows of the whole image).  Clipped to the window.
+  void forward_regions(int first, int n, int upto, const std::vector<Reg> &seed,
+                       std::vector<Reg> &reg) const {
+    const int top = g.top;
+    reg.assign((size_t)n * (top + 1), Reg{0, 0, 0, 0});
+    for (int k = 0; k < n; ++k) {
+      const nst_tile &t = tiles[first + k];
+      int r0 = 0, r1 = 0, c0 = 0, c1 = 0;   // empty
+      for (int i = upto; i >= 0; --i) {
+        if (i < upto && r1 > r0 && c1 > c0) {
+          if (g.pool[i]) {
+            r0 = 2 * (r0 - 1), r1 = 2 * (r1 + 1), c0 = 2 * (c0 - 1), c1 = 2 * (c1 + 1);
+          } else {
+            --r0, ++r1, --c0, ++c1;
+          }
+        }
+        const Reg &s = seed[(size_t)k * (top + 1) + i];
+        if (s[1] > s[0] && s[3] > s[2]) {
+          if (r1 > r0 && c1 > c0) {
+            r0 = std::min(r0, s[0]), r1 = std::max(r1, s[1]), c0 = std::min(c0, s[2]), c1 = std::max(c1, s[3]);
+          } else {
+            r0 = s[0], r1 = s[1], c0 = s[2], c1 = s[3];
+          }
+        }
+        r0 = std::max(r0, 0), r1 = std::min(r1, lh(t, i));
+        c0 = std::max(c0, 0), c1 = std::min(c1, lw(t, i));
+        if (g.pool[i] && i < upto) r0 &= ~1, c0 &= ~1;
+        reg[(size_t)k * (top + 1) + i] = {r0, r1, c0, c1};
+      }
+    }
+  }
+
+  // Forward regions of a pass that needs the owned features of the layers in `layers`
+  // (Step 1: style and content layers; nst_layer_feats: one layer).
+  void owned_forward_regions(int first, int n, int upto, const bool *layers, std::vector<Reg> &reg) const {
+    std::vector<Reg> seed((size_t)n * (g.top + 1), Reg{0, 0, 0, 0});
+    for (int k = 0; k < n; ++k) {
+      const nst_tile &t = tiles[first + k];
+      for (int i = 0; i <= upto; ++i)
+        if (layers[i]) {
+          const int s = g.stride[i], oy = t.ey0 / s, ox = t.ex0 / s;
+          seed[(size_t)k * (g.top + 1) + i] = {t.own[i][0] - oy, t.own[i][1] - oy, t.own[i][2] - ox, t.own[i][3] - ox};
+        }
+    }
+    forward_regions(first, n, upto, seed, reg);
   }
 
   // Grams of the owned features (and, with means, their channel sums) of tiles first..+n
@@ -757,38 +845,17 @@ struct Runner {
     const int vec = (int)(16 / es);
     char *cur = slot_base(L.s_d0), *oth = slot_base(L.s_d1);
     const int top = g.top;
-    // Needed regions (window-local rows r0..r1, columns c0..c1 at conv i's resolution) of
-    // dE/dZ_i: the block's image gradient reads dZ_0 on the block +- 1; dZ_{i-1} on R
-    // comes from the data gradient of conv i on R (through the pool: rows r0 / 2 ..
-    // (r1 + 1) / 2), which reads dZ_i one pixel further out.  Everything the block's
-    // gradient depends on is computed exactly as over the whole window.
-    std::vector<std::array<int, 4>> reg((size_t)n * (top + 1));
-    for (int k = 0; k < n; ++k) {
-      const nst_tile &t = tiles[first + k];
-      int r0 = t.by0 - t.ey0 - 1, r1 = t.by1 - t.ey0 + 1, c0 = t.bx0 - t.ex0 - 1, c1 = t.bx1 - t.ex0 + 1;
-      for (int i = 0; i <= top; ++i) {
-        if (i > 0) {
-          if (g.pool[i - 1]) {
-            r0 = (r0 >> 1) - 1;
-            r1 = ((r1 + 1) >> 1) + 1;
-            c0 = (c0 >> 1) - 1;
-            c1 = ((c1 + 1) >> 1) + 1;
-          } else {
-            --r0, ++r1, --c0, ++c1;
-          }
-        }
-        r0 = std::max(r0, 0), r1 = std::min(r1, lh(t, i));
-        c0 = std::max(c0, 0), c1 = std::min(c1, lw(t, i));
-        reg[(size_t)k * (top + 1) + i] = {r0, r1, c0, c1};
-      }
-    }
+    // Needed regions of dE/dZ_i (backward_regions); everything the block's gradient
+    // depends on is computed exactly as over the whole window.
+    std::vector<Reg> reg;
+    backward_regions(first, n, reg);
     // output region of conv i's data gradient: R_{i-1}, or its pooled rows when a pool
     // follows conv i - 1 (pool = true: the pooled region up to the ceiling of the
     // pre-pool rows, for the pool backward; false: the pooled rows that exist)
     auto out_region = [&](Batch &b, int i, bool pool_bwd) {
       for (int k = 0; k < n; ++k) {
         const nst_tile &t = tiles[first + k];
-        const std::array<int, 4> &r = reg[(size_t)k * (top + 1) + i - 1];
+        const Reg &r = reg[(size_t)k * (top + 1) + i - 1];
         if (!g.pool[i - 1]) {
           b.a0[k] = r[0], b.a1[k] = r[1], b.a2[k] = r[2], b.a3[k] = r[3];
         } else {
@@ -819,7 +886,10 @@ struct Runner {
     };
     {
       Batch b = base_batch(first, n, top);
-      for (int k = 0; k < n; ++k) b.a0[k] = 0, b.a1[k] = b.h[k], b.a2[k] = 0, b.a3[k] = b.w[k];
+      for (int k = 0; k < n; ++k) {
+        const Reg &r = reg[(size_t)k * (top + 1) + top];
+        b.a0[k] = r[0], b.a1[k] = r[1], b.a2[k] = r[2], b.a3[k] = r[3];
+      }
       ConvArgs a;
       std::memset(&a, 0, sizeof(a));
       fill_seeds(a, top);
@@ -858,12 +928,12 @@ struct Runner {
         const bool cont = (i - 1) == g.content && use_content;
         double px = 0;   // pre-pool pixels of the region
         for (int t = 0; t < n; ++t) px += 4.0 * std::max(bp.a1[t] - bp.a0[t], 0) * std::max(bp.a3[t] - bp.a2[t], 0);
-        HIPCHK(prof(c->prec == 1 ? "void nst::k_pool_bwd<__bf16>(__bf16 const*, long long, __bf16 const*, long long, float const*, long long, float, __bf16*, long long, int, nst::Batch)"
-                                 : "void nst::k_pool_bwd<float>(float const*, long long, float const*, long long, float const*, long long, float, float*, long long, int, nst::Batch)",
+        HIPCHK(prof(c->prec == 1 ? "void nst::k_pool_bwd<__bf16>(__bf16 const*, long long, __bf16 const*, long long, float const*, long long, float, __bf16*, long long, int, bool, nst::Batch)"
+                                 : "void nst::k_pool_bwd<float>(float const*, long long, float const*, long long, float const*, long long, float, float*, long long, int, bool, nst::Batch)",
                     0.0, 2.25 * px * C * es + (cont ? 4.0 * px * C : 0.0), [&] {
                       return launch_pool_bwd(c->prec, oth, ss(es), slot_base(L.s_act[i - 1]), ss(es),
                                              cont ? (const float *)slot_base(L.s_rc) : nullptr, ss(4),
-                                             two_alpha, cur, ss(es), C, bp, s);
+                                             two_alpha, cur, ss(es), C, g.pavg[i - 1], bp, s);
                     }));
       } else {
         std::swap(cur, oth);
@@ -972,7 +1042,19 @@ int step1(Runner &R, const float *x, const float *fc, bool keep, bool means) {
   const int nt = (int)R.tiles.size();
   for (int first = 0; first < nt; first += R.L.batch) {
     const int n = std::min(R.L.batch, nt - first);
-    int st = R.forward(first, n, upto, x, fc, keep);
+    // the owned style / content features, or (activations kept for Step 2) what Step 2 needs
+    std::vector<Reg> regions;
+    if (keep) {
+      std::vector<Reg> need;
+      R.backward_regions(first, n, need);
+      R.forward_regions(first, n, upto, need, regions);
+    } else {
+      bool layers[NST_MAX_CONV] = {};
+      for (int k = 0; k < g.n_style; ++k) layers[g.style[k]] = true;
+      if (fc) layers[g.content] = true;
+      R.owned_forward_regions(first, n, upto, layers, regions);
+    }
+    int st = R.forward(first, n, upto, x, fc, keep, regions);
     if (st != NST_OK) return st;
     if ((st = R.grams(first, n, means)) != NST_OK) return st;
     if (fc && (st = R.content_energy(first, n)) != NST_OK) return st;
@@ -1069,7 +1151,11 @@ int nst_layer_feats(nst_ctx *ctx, const float *img, int H, int W, int T, int m, 
   const int vec = (int)(16 / R.L.es);
   for (int first = 0; first < nt; first += R.L.batch) {
     const int n = std::min(R.L.batch, nt - first);
-    if ((st = R.forward(first, n, conv, img, nullptr, false)) != NST_OK) return st;
+    bool layers[NST_MAX_CONV] = {};
+    layers[conv] = true;
+    std::vector<Reg> regions;
+    R.owned_forward_regions(first, n, conv, layers, regions);
+    if ((st = R.forward(first, n, conv, img, nullptr, false, regions)) != NST_OK) return st;
     Batch b = R.base_batch(first, n, conv);
     std::vector<long long> items(n);
     for (int t = 0; t < n; ++t) items[t] = (long long)Runner::region_px(b, t) * (ctx->g.cout[conv] / vec);
@@ -1171,7 +1257,13 @@ int nst_loss_grad_ms(nst_ctx *ctx, const float *x, int H, int W, const double *t
       const int n = std::min(R.L.batch, nt - first);
       // Step 1 of this call left every tile's activations (and content difference) in its
       // slot when each tile has one; otherwise Step 2 recomputes them (Algorithm 1)
-      if (!(s1 && R.retain) && (st = R.forward(first, n, g.top, x, fc, true)) != NST_OK) return st;
+      if (!(s1 && R.retain)) {
+        // the forward on what the data gradients read (masks, residual operands, pools)
+        std::vector<Reg> need, regions;
+        R.backward_regions(first, n, need);
+        R.forward_regions(first, n, g.top, need, regions);
+        if ((st = R.forward(first, n, g.top, x, fc, true, regions)) != NST_OK) return st;
+      }
       if (!s1 && fc && (st = R.content_energy(first, n)) != NST_OK) return st;
       if ((st = R.backward(first, n, (float)(2.0 * alpha), use_c, use_ms, grad)) != NST_OK) return st;
     }

@@ -17,9 +17,12 @@ from ._lib import (NST_BF16, NST_BOTH, NST_CHECK_FINITE, NST_FP32, NST_RESIDENT,
 PRECISIONS = {"fp32": NST_FP32, "bf16": NST_BF16}
 
 
-def vgg19_desc(tiny: bool = False, with_content: bool = True) -> NetDesc:
+def vgg19_desc(tiny: bool = False, with_content: bool = True, avg_pool: bool = False) -> NetDesc:
+    """The VGG-19 prefix; avg_pool replaces every max pool by a 2x2 average pool."""
     d = NetDesc()
     check("nst_net_vgg19", lib().nst_net_vgg19(byref(d), int(tiny), int(with_content)))
+    if avg_pool:
+        d.pool_avg = d.pool_after
     return d
 
 
@@ -89,11 +92,11 @@ class Context:
 
     def __init__(self, weights, biases=None, precision: str = "fp32", desc: NetDesc | None = None,
                  tiny: bool = False, with_content: bool = True, ws_limit: int = 96 << 30,
-                 tile_batch: int = 32, resident: bool = False):
+                 tile_batch: int = 32, resident: bool = False, avg_pool: bool = False):
         """resident: keep every tile's activations from Step 1 to Step 2 of a loss_grad call
         (NST_RESIDENT, a workspace for every tile) instead of recomputing them per tile
         batch as Algorithm 1 does."""
-        self.desc = desc if desc is not None else vgg19_desc(tiny, with_content)
+        self.desc = desc if desc is not None else vgg19_desc(tiny, with_content, avg_pool)
         self.convs, self.style, self.content = desc_info(self.desc)
         self.precision = precision
         self.device = torch.device("cuda", torch.cuda.current_device())

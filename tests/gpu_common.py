@@ -8,7 +8,7 @@ import oracle
 import synth
 from oracle import bf16ref
 from oracle.loss import MeanStd, content_features, loss_grad, style_grams, style_stats
-from oracle.ops import conv3x3, maxpool2, relu
+from oracle.ops import avgpool2, conv3x3, maxpool2, relu
 
 
 def rel(a, b):
@@ -128,10 +128,14 @@ def gpu_acts(nst, x_d, T, m, top):
     return out
 
 
-def layer_input(net, acts, i, x0):
+def layer_input(net, acts, i, x0, q=bf16ref.identity):
+    """Input of conv i built from the GPU's stored features: the image, the previous
+    layer, or its pool (an average pool's mean is stored rounded, like the kernels do)."""
     if i == 0:
         return x0
-    return maxpool2(acts[i - 1]) if (i - 1) in net.pool_after else acts[i - 1]
+    if (i - 1) not in net.pool_after:
+        return acts[i - 1]
+    return q(avgpool2(acts[i - 1])) if net.avg_pool else maxpool2(acts[i - 1])
 
 
 def bf16_units_apart(a, b):
@@ -146,7 +150,7 @@ def check_forward(net, acts, ws, bs, x, prec, label):
     x0 = q(np.asarray(x, np.float64))
     worst = []
     for i in range(len(acts)):
-        ref = q(relu(conv3x3(layer_input(net, acts, i, x0), q(ws[i]), bs[i])))
+        ref = q(relu(conv3x3(layer_input(net, acts, i, x0, q), q(ws[i]), bs[i])))
         a = acts[i]
         assert a.shape == ref.shape, (i, a.shape, ref.shape)
         rms = float(np.sqrt(np.mean(ref * ref))) or 1.0

@@ -39,9 +39,21 @@ def test_library_exports_every_declared_symbol(L):
 
 
 def test_abi_version_and_strerror(L):
-    assert L.nst_abi_version() == 1
+    assert L.nst_abi_version() == 2
     assert L.nst_strerror(0) == b"ok"
     assert L.nst_strerror(-7) == b"workspace too small"
+    assert L.nst_strerror(-8) == b"non-finite value in an input"
+
+
+def test_pool_avg_bits_must_be_pools(L):
+    """nst_net_desc.pool_avg may only mark convs that a pool follows."""
+    import ctypes
+    from paper_2212_13459_amd.nst import vgg19_desc
+    d = vgg19_desc(avg_pool=True)
+    assert d.pool_avg == d.pool_after
+    assert L.nst_min_halo(ctypes.byref(d)) == 155
+    d.pool_avg = d.pool_after | 1   # conv1_1 is not followed by a pool
+    assert L.nst_min_halo(ctypes.byref(d)) == -1
 
 
 def test_min_halo_matches_oracle():

@@ -26,13 +26,15 @@ forward every element within one BF16 unit of the reference and at most 1e-3 of 
 elements off by one unit, Grams <= 1e-6, energies <= 1e-5 (content) / 1e-12 (style),
 gradient <= 1e-2 (the adjoints are stored in BF16 at every layer).
 """
+import dataclasses
+
 import numpy as np
 import pytest
 import torch
 
 from gpu_common import (case, check_forward, cuda, fc_hwc, flat_grams, gpu_acts, layer_input, mean_std,
                         oracle_targets, quant, rel, seeds_on)
-from oracle.loss import channel_mean, std_from_stats
+from oracle.loss import channel_mean, content_features, std_from_stats, style_grams
 from oracle import bf16ref
 from oracle.loss import gram
 from oracle.ops import conv3x3, relu
@@ -59,29 +61,33 @@ def need_gpu():
 _ctx = {}
 
 
-def ctx(kind, prec, with_content=True):
+def ctx(kind, prec, with_content=True, avg_pool=False):
     from paper_2212_13459_amd import Context
-    key = (kind, prec, with_content)
+    key = (kind, prec, with_content, avg_pool)
     if key not in _ctx:
         k = case(kind, 8, 8, 8, 8, 1.0)
-        _ctx[key] = Context(k["ws"], k["bs"], prec, tiny=(kind == "tiny"), with_content=with_content)
+        _ctx[key] = Context(k["ws"], k["bs"], prec, tiny=(kind == "tiny"), with_content=with_content,
+                            avg_pool=avg_pool)
     return _ctx[key]
 
 
-def run_stages(name, prec, alpha=1.0, w_style=None, with_content=True, msw=None):
+def run_stages(name, prec, alpha=1.0, w_style=None, with_content=True, msw=None, avg_pool=False):
     spec, T, m = CONFIGS[name]
     kind, H, W, Hs, Ws, sigma = spec
     k = case(*spec)
-    net = k["net"] if with_content else k["net"].__class__(
-        convs=k["net"].convs, pool_after=k["net"].pool_after, style=k["net"].style, content=None)
+    net = dataclasses.replace(k["net"], content=k["net"].content if with_content else None, avg_pool=avg_pool)
     if w_style is None:
         w_style = W3 if kind == "tiny" else W5
     if not with_content:
         alpha = 0.0
-    nst = ctx(kind, prec, with_content)
+    nst = ctx(kind, prec, with_content, avg_pool)
     ws = [w.astype(np.float64) for w in k["ws"]]
     bs = [b.astype(np.float64) for b in k["bs"]]
-    g_t, f_c = oracle_targets(*spec)
+    if avg_pool:
+        g_t = style_grams(net, k["s"].astype(np.float64), ws, bs)
+        f_c = content_features(dataclasses.replace(net, content=k["net"].content), k["c"].astype(np.float64), ws, bs)
+    else:
+        g_t, f_c = oracle_targets(*spec)
     f_c32 = f_c.astype(np.float32).astype(np.float64)
     gt_d = cuda(flat_grams(g_t), torch.float64)
     fc_d = cuda(fc_hwc(f_c)) if with_content else None
@@ -117,7 +123,7 @@ def run_stages(name, prec, alpha=1.0, w_style=None, with_content=True, msw=None)
     raw_c, ec_err = None, 0.0
     if net.content is not None:
         i = net.content
-        raw_c = relu(conv3x3(layer_input(net, acts, i, q(np.asarray(k["x"], np.float64))), q(ws[i]), bs[i]))
+        raw_c = relu(conv3x3(layer_input(net, acts, i, q(np.asarray(k["x"], np.float64)), q), q(ws[i]), bs[i]))
         if alpha != 0.0:
             e_c = alpha * float(np.sum((raw_c - f_c32) ** 2))
             ec_err = abs(energy[1] - e_c) / e_c
@@ -173,3 +179,10 @@ def test_stages_mean_std(name, prec):
     features, the augmented energy terms, and the Step 2 gradient with the mean and std
     rows of Table 1 on the GPU's own activations."""
     run_stages(name, prec, msw=MSW3 if name == "tiny" else MSW5)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("name", ["tiny", "ragged"])
+def test_stages_average_pooling(name, prec):
+    """The network with every max pool replaced by a 2x2 average pool."""
+    run_stages(name, prec, avg_pool=True)

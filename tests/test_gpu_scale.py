@@ -250,7 +250,7 @@ def test_stages_at_scale(name, prec):
         sc = strides[ic]
         oy, ox = t.ey0 // sc, t.ex0 // sc
         hl, wl = acts[ic].shape[1:]
-        raw_c = relu(conv3x3(layer_input(NET, acts, ic, q(xw.astype(np.float64))), q(ws[ic]), bs[ic]))
+        raw_c = relu(conv3x3(layer_input(NET, acts, ic, q(xw.astype(np.float64)), q), q(ws[ic]), bs[ic]))
         seeds = seeds_on(NET, acts, raw_c, grams_x, g_t, fc_h[:, oy:oy + hl, ox:ox + wl], W5, 1.0, prec, n_ps)
         g_ref = bf16ref.backward(NET, acts, seeds, ws, q)
         inner_ref = g_ref[:, t.by0 - t.ey0:t.by1 - t.ey0, t.bx0 - t.ex0:t.bx1 - t.ex0]
@@ -300,7 +300,7 @@ def test_whole_image_stages_2048(prec, alpha, w_style):
     gerr = [rel(G, gram(acts[i], acts[i].shape[1] * acts[i].shape[2])) for G, i in zip(grams_x, NET.style)]
     _, _, grad = nst.loss_grad(x, gt, fc, w_style, alpha, T, m, flags=2, grams_x=gx.clone())
     ic = NET.content
-    raw_c = relu(conv3x3(layer_input(NET, acts, ic, q(xh.astype(np.float64))), q(ws[ic]), bs[ic]))
+    raw_c = relu(conv3x3(layer_input(NET, acts, ic, q(xh.astype(np.float64)), q), q(ws[ic]), bs[ic]))
     seeds = seeds_on(NET, acts, raw_c, grams_x, g_t, fc.permute(2, 0, 1).double().cpu().numpy(), w_style, alpha,
                      prec)
     g_ref = bf16ref.backward(NET, acts, seeds, ws, q)

@@ -549,3 +549,92 @@ def test_relu_flip_into_all_zero_pool_window():
     full[:, Y0:Y1, X0:X1] = d
     assert np.abs(g_flip - g - full).max() <= 1e-12 * np.abs(g).max()
     assert np.abs(full).max() > 0
+
+
+# ------------------------------------------------- average-pooling variant --
+
+def test_avgpool_matches_loops_and_torch():
+    rng = np.random.default_rng(50)
+    for h, w in ((6, 8), (7, 9), (5, 4)):
+        a = rng.standard_normal((3, h, w))
+        ref = np.zeros((3, h // 2, w // 2))
+        for c in range(3):
+            for y in range(h // 2):
+                for x in range(w // 2):
+                    ref[c, y, x] = (a[c, 2 * y, 2 * x] + a[c, 2 * y, 2 * x + 1] + a[c, 2 * y + 1, 2 * x]
+                                    + a[c, 2 * y + 1, 2 * x + 1]) / 4.0
+        assert np.allclose(ops.avgpool2(a), ref, rtol=0, atol=1e-15)
+        t = F.avg_pool2d(torch.from_numpy(a)[None], 2, 2)[0].numpy()
+        assert np.allclose(ops.avgpool2(a), t, rtol=0, atol=1e-15)
+        dy = rng.standard_normal((3, h // 2, w // 2))
+        # adjoint identity <pool(a), dy> = <a, pool^T(dy)>; dropped rows get 0
+        lhs = float(np.sum(ops.avgpool2(a) * dy))
+        g = ops.avgpool2_backward(dy, a)
+        assert abs(lhs - float(np.sum(a * g))) < 1e-12
+        if h % 2:
+            assert np.all(g[:, -1, :] == 0.0)
+
+
+def torch_energy_avg(net, x, ws, bs, grams_t, f_c, w_style, alpha):
+    a = x
+    acts = {}
+    for i in range(max(list(net.style) + [net.content]) + 1):
+        a = F.relu(F.conv2d(a, ws[i], bs[i], padding=1))
+        acts[i] = a
+        if i in net.pool_after:
+            a = F.avg_pool2d(a, 2, 2)
+    e = torch.zeros((), dtype=torch.float64)
+    for k, i in enumerate(net.style):
+        v = acts[i][0].reshape(acts[i].shape[1], -1).T
+        e = e + w_style[k] * torch.sum((v.T @ v / v.shape[0] - grams_t[k]) ** 2)
+    return e + alpha * torch.sum((acts[net.content][0] - f_c) ** 2)
+
+
+@pytest.mark.parametrize("kind", ["tiny", "full"])
+def test_avgpool_net_loss_grad_matches_torch_autograd(kind):
+    net = vgg19_tiny(avg_pool=True) if kind == "tiny" else vgg19(avg_pool=True)
+    h, w = (26, 30) if kind == "tiny" else (36, 52)
+    ws, bs = synth.vgg_weights(net.convs, seed=0, bias_std=0.02)
+    ws = [wi.astype(np.float64) for wi in ws]
+    bs = [bi.astype(np.float64) for bi in bs]
+    c = synth.image(h, w, 4, 1).astype(np.float64)
+    s = synth.image(h + 4, w - 4, 4, 2).astype(np.float64)
+    x = synth.image(h, w, 4, 3).astype(np.float64)
+    g_t = oracle.loss.style_grams(net, s, ws, bs)
+    f_c = oracle.content_features(net, c, ws, bs)
+    ns = len(net.style)
+    w_style = [1.0 / ns] * ns
+    terms, grad = loss_grad(net, x, ws, bs, g_t, f_c, w_style, 0.5)
+    tx = torch.from_numpy(x)[None].requires_grad_(True)
+    e = torch_energy_avg(net, tx, [torch.from_numpy(v) for v in ws], [torch.from_numpy(v) for v in bs],
+                         [torch.from_numpy(v) for v in g_t], torch.from_numpy(f_c), w_style, 0.5)
+    e.backward()
+    assert abs(terms["E"] - e.item()) <= 1e-12 * abs(e.item())
+    assert rel(grad, tx.grad[0].numpy()) < 1e-11
+    # and it is not the max-pool network's value
+    net_max = vgg19_tiny() if kind == "tiny" else vgg19()
+    assert abs(loss_grad(net_max, x, ws, bs, g_t, f_c, w_style, 0.5, want_grad=False)[0]["E"] - terms["E"]) > 1e-6
+
+
+def test_avgpool_net_tiled_equals_whole():
+    net = vgg19_tiny(avg_pool=True)
+    whole, gw, tiled, gt, _ = _tiled_vs_whole(net, 70, 58, 16, 23)
+    for a, b in zip(tiled["grams"], whole["grams"]):
+        assert rel(a, b) < 1e-13
+    assert rel(gt, gw) < 1e-12
+
+
+def test_avgpool_bf16_reference_with_rounding_off_is_the_oracle():
+    from oracle import bf16ref
+    net = vgg19_tiny(avg_pool=True)
+    ws, bs = synth.vgg_weights(net.convs, seed=0, bias_std=0.02)
+    ws = [wi.astype(np.float64) for wi in ws]
+    bs = [bi.astype(np.float64) for bi in bs]
+    x = synth.image(24, 28, 4, 3).astype(np.float64)
+    c = synth.image(24, 28, 4, 1).astype(np.float64)
+    s = synth.image(28, 24, 4, 2).astype(np.float64)
+    g_t = oracle.loss.style_grams(net, s, ws, bs)
+    f_c = oracle.content_features(net, c, ws, bs)
+    t0, g0 = loss_grad(net, x, ws, bs, g_t, f_c, [1 / 3] * 3, 1.0)
+    t1, g1 = bf16ref.loss_grad(net, x, ws, bs, g_t, f_c, [1 / 3] * 3, 1.0, q=bf16ref.identity)
+    assert t0["E"] == t1["E"] and np.array_equal(g0, g1)
