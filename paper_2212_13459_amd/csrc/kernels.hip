@@ -78,169 +78,6 @@ __device__ __forceinline__ int find_tile(const Batch &g, int bid) {
 }
 
 // ---------------------------------------------------------------------------------------
-// Implicit-GEMM 3x3 convolution on MFMA.
-//   M = output pixels of a PH x 16 spatial patch, N = BN output channels, K = taps x cin.
-//   Segment 0: the 9 taps over `in` (halo patch staged in LDS) or, for the image input,
-//              an im2col of the 27 (tap, colour) values padded to 32.
-//   Segment 1: the centre tap over `in2` (the style residual V D~ of the data gradient).
-//   Epilogues: forward bias+ReLU (+ fp32 content difference), backward content residual
-//   + ReLU mask, or the image-gradient stitch of the block's inner pixels.
-// 256 threads = 4 waves in a WM x WN grid, each wave TM x TN blocks of 32x32.
-// ---------------------------------------------------------------------------------------
-template <typename T, int PH, int BN, int WM, int WN, int IN, int EPI, bool SEG2>
-__global__ __launch_bounds__(256) void k_conv(ConvArgs a, Batch g) {
-  constexpr int PW = 16, BM = PH * PW;
-  constexpr int TM = BM / (WM * 32), TN = BN / (WN * 32);
-  static_assert(WM * WN == 4 && TM >= 1 && TN >= 1, "bad wave tiling");
-  constexpr int CK = Tr<T>::CK;
-  constexpr int VEC = 16 / sizeof(T);
-  constexpr int ST = CK + VEC;                       // LDS row stride: 16-byte pad
-  constexpr int HP = PH + 2, WP = PW + 2;
-  constexpr int APIX = (IN == IN_IMAGE) ? BM : HP * WP;
-  constexpr int NTAPB = (IN == IN_NHWC) ? 9 : 1;
-  __shared__ __attribute__((aligned(16))) T As[APIX * ST];
-  __shared__ __attribute__((aligned(16))) T Bs[NTAPB * BN * ST];
-
-  const int t = find_tile(g, blockIdx.x);
-  const int lb = blockIdx.x - g.pfx[t];
-  const int h = g.h[t], w = g.w[t];
-  const int nbx = (g.a3[t] - g.a2[t] + PW - 1) / PW;   // output region a0..a3
-  const int y0 = g.a0[t] + (lb / nbx) * PH, x0 = g.a2[t] + (lb % nbx) * PW;
-  const int n0 = blockIdx.y * BN;
-  const long long slot = g.slot[t];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave / WN, wn = wave % WN;
-  const int l32 = lane & 31, half = lane >> 5;
-
-  int pidx[TM];
-#pragma unroll
-  for (int tm = 0; tm < TM; ++tm) {
-    const int m = wm * TM * 32 + tm * 32 + l32;
-    pidx[tm] = (IN == IN_IMAGE) ? m : (m / PW) * WP + (m % PW);
-  }
-
-  f32x16 acc[TM][TN];
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
-
-#pragma unroll 1
-  for (int seg = 0; seg < 2; ++seg) {
-    if (seg == 0 && IN == IN_NONE) continue;
-    if (seg == 1 && !SEG2) continue;
-    const T *src = (const T *)(seg == 0 ? a.in : a.in2);
-    const long long ss = seg == 0 ? a.in_ss : a.in2_ss;
-    const int cin = seg == 0 ? (IN == IN_IMAGE ? 32 : a.cin) : a.cin2;
-    const T *wsrc = (const T *)(seg == 0 ? a.wp : a.wp2);
-    const int ntap = (seg == 0 && IN == IN_NHWC) ? 9 : 1;
-    const int nck = cin / CK;
-    const T *base = (seg == 0 && IN == IN_IMAGE) ? nullptr : src + slot * ss;
-
-#pragma unroll 1
-    for (int ck = 0; ck < nck; ++ck) {
-      __syncthreads();
-      if (seg == 0 && IN == IN_IMAGE) {
-        for (int e = tid; e < BM * CK; e += 256) {
-          const int m = e / CK, kk = e - m * CK, k = ck * CK + kk;
-          const int py = y0 + m / PW, px = x0 + m % PW;
-          float v = 0.f;
-          if (k < 27 && py < h && px < w) {
-            const int tap = k / 3, c = k - tap * 3;
-            const int yy = py + tap / 3 - 1, xx = px + tap % 3 - 1;
-            if (yy >= 0 && yy < h && xx >= 0 && xx < w)
-              v = a.img[((long long)c * a.img_h + (g.gy[t] + yy)) * a.img_w + (g.gx[t] + xx)];
-          }
-          As[m * ST + kk] = from_f<T>(v);
-        }
-      } else {
-        for (int v = tid; v < HP * WP * 4; v += 256) {
-          const int pix = v >> 2, part = v & 3;
-          const int py = pix / WP, px = pix - py * WP;
-          const int yy = y0 - 1 + py, xx = x0 - 1 + px;
-          uint4 val = make_uint4(0u, 0u, 0u, 0u);
-          if (yy >= 0 && yy < h && xx >= 0 && xx < w)
-            val = *(const uint4 *)(base + ((long long)yy * w + xx) * cin + ck * CK + part * VEC);
-          *(uint4 *)(&As[pix * ST + part * VEC]) = val;
-        }
-      }
-      {
-        const T *wb = wsrc + ((long long)ck * ntap) * a.cout_pad * CK;
-        const int nvec = ntap * BN * 4;
-        for (int v = tid; v < nvec; v += 256) {
-          const int row = v >> 2, part = v & 3;
-          const int tap = row / BN, n = row - tap * BN;
-          const uint4 val =
-              *(const uint4 *)(wb + ((long long)tap * a.cout_pad + n0 + n) * CK + part * VEC);
-          *(uint4 *)(&Bs[row * ST + part * VEC]) = val;
-        }
-      }
-      __syncthreads();
-
-#pragma unroll 1
-      for (int tap = 0; tap < ntap; ++tap) {
-        int toff;
-        if (seg == 0 && IN == IN_IMAGE) toff = 0;
-        else if (ntap == 9) toff = (tap / 3) * WP + (tap % 3);
-        else toff = WP + 1;
-        typename Mma<T>::Frag af[TM], bfr[TN];
-#pragma unroll
-        for (int tm = 0; tm < TM; ++tm)
-          af[tm] = Mma<T>::load(&As[(pidx[tm] + toff) * ST + half * (CK / 2)]);
-#pragma unroll
-        for (int tn = 0; tn < TN; ++tn) {
-          const int n = wn * TN * 32 + tn * 32 + l32;
-          bfr[tn] = Mma<T>::load(&Bs[(tap * BN + n) * ST + half * (CK / 2)]);
-        }
-#pragma unroll
-        for (int tm = 0; tm < TM; ++tm)
-#pragma unroll
-          for (int tn = 0; tn < TN; ++tn) Mma<T>::mma(acc[tm][tn], af[tm], bfr[tn]);
-      }
-    }
-  }
-
-  // epilogue: D[m][n] of a 32x32 block sits in lane (n, m/4 mod 2) register
-  // 4 (m / 8) + m mod 4.
-  const int cout = a.cout;
-#pragma unroll
-  for (int tm = 0; tm < TM; ++tm)
-#pragma unroll
-    for (int tn = 0; tn < TN; ++tn)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int m = wm * TM * 32 + tm * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
-        const int py = y0 + m / PW, px = x0 + m % PW;
-        const int n = n0 + wn * TN * 32 + tn * 32 + l32;
-        if (py >= h || px >= w || n >= cout) continue;
-        const long long pix = (long long)py * w + px;
-        float v = acc[tm][tn][r];
-        if (EPI == EPI_FWD) {
-          v = fmaxf(v + a.bias[n], 0.f);
-          ((T *)a.out)[slot * a.out_ss + pix * cout + n] = from_f<T>(v);
-          if (a.rc) {
-            const float f =
-                a.fc[((long long)(g.gy[t] + py) * a.fc_w + (g.gx[t] + px)) * cout + n];
-            a.rc[slot * a.rc_ss + pix * cout + n] = v - f;
-          }
-        } else if (EPI == EPI_BWD) {
-          if (a.bias) v += a.bias[n];
-          if (a.rc) v += a.two_alpha * a.rc[slot * a.rc_ss + pix * cout + n];
-          if (a.mask) {
-            const float mk = to_f(((const T *)a.mask)[slot * a.mask_ss + pix * cout + n]);
-            if (!(mk > 0.f)) v = 0.f;
-          }
-          ((T *)a.out)[slot * a.out_ss + pix * cout + n] = from_f<T>(v);
-        } else {
-          if (py >= g.a0[t] && py < g.a1[t] && px >= g.a2[t] && px < g.a3[t])
-            a.grad[((long long)n * a.img_h + (g.gy[t] + py)) * a.img_w + (g.gx[t] + px)] = v;
-        }
-      }
-}
-
-// ---------------------------------------------------------------------------------------
 // Pipelined implicit-GEMM 3x3 convolution (NHWC input) on MFMA.
 //   Work block: a PH x 32 output patch (M = 32 PH pixels) x BN output channels, WM x WN
 //   waves.  The K loop runs over stages (channel chunk c, filter row ky): each stage holds
@@ -959,13 +796,20 @@ __global__ __launch_bounds__(WM * WN * 64, SA ? (BN <= 64 ? 3 : 2) : 1) void k_c
     const bool ok = row < AROWS && unit < 4 && yy >= 0 && yy < h && xx >= 0 && xx < w;
     okbits |= (ok ? 1u : 0u) << i;
   }
-  dma_boff<T, NT, BNV, BN, CK, VEC>(boff, 3, a.cout_pad, n0, tid);
-  const T *abase0 = in0 + ((long long)by * w + bx) * a.cin;
+  // no 3x3 segment (nck = 0: the top layer's seeds): the first stage is segment 1's
+  const bool seg1_first = nck == 0;
+  dma_boff<T, NT, BNV, BN, CK, VEC>(boff, seg1_first ? 1 : 3, a.cout_pad, n0, tid);
+  const T *abase0 = seg1_first ? nullptr : in0 + ((long long)by * w + bx) * a.cin;
   const long long wrow = (long long)a.cout_pad * CK;
 
   T *const A0 = sm, *const A1 = sm + (NA - 1) * ASZ, *const B0 = sm + NA * ASZ, *const B1 = sm + NA * ASZ + BSZ;
-  dma_a<T, NT, ANVD, VEC>(A0, abase0, arel, okbits, a.cin, wv, tid);
-  dma_b<T, NT, BNV, VEC>(B0, wp0, boff, wv);
+  if (!seg1_first) {
+    dma_a<T, NT, ANVD, VEC>(A0, abase0, arel, okbits, a.cin, wv, tid);
+    dma_b<T, NT, BNV, VEC>(B0, wp0, boff, wv);
+  } else if (nck2 > 0) {
+    dma_a<T, NT, ANVD, VEC>(A0, in1 + ((long long)by * w + bx) * a.cin2, arel, okbits, a.cin2, wv, tid);
+    dma_b<T, NT, BNV, VEC>(B0, wp1, boff, wv);
+  }
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   const int bcol = wn * TN * 32 + l32;
@@ -974,7 +818,8 @@ __global__ __launch_bounds__(WM * WN * 64, SA ? (BN <= 64 ? 3 : 2) : 1) void k_c
   // each stage passes the workgroup barrier itself and leaves the next stage's first
   // fragments in fr[0]
   KFrag<TM, TN> fr[2];
-  load_kstep<T, TM, TN, BN, CK, VEC>(fr[0], A0, B0, pidx, 0, 0, 0, bcol, half);
+  if (!seg1_first || nck2 > 0)
+    load_kstep<T, TM, TN, BN, CK, VEC>(fr[0], A0, B0, pidx, seg1_first ? WP + 1 : 0, 0, 0, bcol, half);
   if constexpr (SA) {
     // one halo buffer A0: each chunk's last stage issues the next halo chunk (or segment
     // 1's first) halfway through its last k-step; the wait and barrier follow the stage
@@ -1227,15 +1072,6 @@ __global__ __launch_bounds__(256, kImgBlocksPerCU<T>) void k_conv_img(ConvArgs a
   }
 }
 
-template <typename T, int PH, int BN, int WM, int WN, int IN, int EPI, bool SEG2>
-static hipError_t run_conv(const ConvArgs &a, const Batch &g, hipStream_t s) {
-  const int nblk = g.pfx[g.n];
-  if (nblk == 0) return hipSuccess;
-  dim3 grid(nblk, (a.cout + BN - 1) / BN);
-  hipLaunchKernelGGL((k_conv<T, PH, BN, WM, WN, IN, EPI, SEG2>), grid, dim3(256), 0, s, a, g);
-  return hipGetLastError();
-}
-
 // k_conv3 tile configurations: BN output channels, WM x WN waves, PH x 32 pixel patches,
 // sa = one halo buffer.  BF16 layers with 256 or 512 channels (long K loops) use 4 waves
 // with 128 x 128 wave tiles (AGPR accumulators, one block and one wave per SIMD).
@@ -1256,14 +1092,12 @@ static Conv2Cfg conv2_cfg(int precision, int cout) {
 }
 
 int conv_block_rows(int precision, int in_mode, int epi, int cout) {
-  (void)precision;
   if (epi == EPI_STITCH || in_mode == IN_IMAGE) return 8;   // k_conv3 stitch, k_conv_img
-  if (in_mode == IN_NHWC) return conv2_cfg(precision, cout).ph;   // k_conv3
-  return cout <= 64 ? 16 : 8;
+  return conv2_cfg(precision, cout).ph;                      // k_conv3
 }
 int conv_block_cols(int precision, int in_mode, int epi, int cout) {
-  (void)precision; (void)cout;
-  return (in_mode == IN_NHWC || in_mode == IN_IMAGE) ? 32 : 16;
+  (void)precision; (void)in_mode; (void)epi; (void)cout;
+  return 32;
 }
 int conv_block_px(int precision, int in_mode, int epi, int cout) {
   return conv_block_cols(precision, in_mode, epi, cout) * conv_block_rows(precision, in_mode, epi, cout);
@@ -1310,8 +1144,9 @@ static hipError_t conv_dispatch(int in_mode, int epi, const ConvArgs &a, const B
       return run_conv3<T, 128, 4, 2, 8, EPI_FWD, false>(a, g, s);
     }
   }
-  // EPI_BWD
-  if (in_mode == IN_NHWC) {
+  // EPI_BWD; IN_NONE: no 3x3 segment (the top layer's seeds: segment 1 and the epilogue)
+  if (in_mode == IN_NONE && (a.cin != 0 || a.in != nullptr)) return hipErrorInvalidValue;
+  if (in_mode == IN_NHWC || in_mode == IN_NONE) {
 #define NST_CONV3_BWD(BN_, WM_, WN_, PH_, RC_, SA_)                                        \
   return seg2 ? run_conv3<T, BN_, WM_, WN_, PH_, EPI_BWD, true, RC_, SA_>(a, g, s)        \
               : run_conv3<T, BN_, WM_, WN_, PH_, EPI_BWD, false, RC_, SA_>(a, g, s)
@@ -1331,13 +1166,6 @@ static hipError_t conv_dispatch(int in_mode, int epi, const ConvArgs &a, const B
     }
 #undef NST_CONV3_BWD
   }
-  if (in_mode == IN_NONE) {
-    if (small)
-      return seg2 ? run_conv<T, 16, 64, 4, 1, IN_NONE, EPI_BWD, true>(a, g, s)
-                  : run_conv<T, 16, 64, 4, 1, IN_NONE, EPI_BWD, false>(a, g, s);
-    return seg2 ? run_conv<T, 8, 128, 2, 2, IN_NONE, EPI_BWD, true>(a, g, s)
-                : run_conv<T, 8, 128, 2, 2, IN_NONE, EPI_BWD, false>(a, g, s);
-  }
   return hipErrorInvalidValue;
 }
 
@@ -1346,30 +1174,18 @@ const char *conv_kernel_name(int precision, int in_mode, int epi, const ConvArgs
   static int k = 0;
   char *o = buf[k++ & 7];
   const bool seg2 = a.in2 != nullptr && a.cin2 > 0;
-  int ph, bn, wm, wn;
+  const char *ty = precision == 1 ? "__bf16" : "float";
   if (in_mode == IN_IMAGE) {
-    snprintf(o, 160, "void nst::k_conv_img<%s>(nst::ConvArgs, nst::Batch)", precision == 1 ? "__bf16" : "float");
-    return o;
-  }
-  if (in_mode == IN_NHWC && epi != EPI_STITCH) {
+    snprintf(o, 160, "void nst::k_conv_img<%s>(nst::ConvArgs, nst::Batch)", ty);
+  } else if (epi == EPI_STITCH) {
+    snprintf(o, 160, "void nst::k_conv3<%s, 32, 4, 1, 8, %d, false, false, true>(nst::ConvArgs, nst::Batch)", ty,
+             EPI_STITCH);
+  } else {
     const Conv2Cfg k = conv2_cfg(precision, a.cout);
     const bool f32e = precision == 1 && a.rc != nullptr;
-    snprintf(o, 160, "void nst::k_conv3<%s, %d, %d, %d, %d, %d, %s, %s, %s>(nst::ConvArgs, nst::Batch)",
-             precision == 1 ? "__bf16" : "float", k.bn, k.wm, k.wn, k.ph, epi, seg2 ? "true" : "false",
-             f32e ? "true" : "false", k.sa ? "true" : "false");
-    return o;
+    snprintf(o, 160, "void nst::k_conv3<%s, %d, %d, %d, %d, %d, %s, %s, %s>(nst::ConvArgs, nst::Batch)", ty, k.bn,
+             k.wm, k.wn, k.ph, epi, seg2 ? "true" : "false", f32e ? "true" : "false", k.sa ? "true" : "false");
   }
-  if (epi == EPI_STITCH) {
-    snprintf(o, 160, "void nst::k_conv3<%s, 32, 4, 1, 8, %d, false, false, true>(nst::ConvArgs, nst::Batch)",
-             precision == 1 ? "__bf16" : "float", EPI_STITCH);
-    return o;
-  } else if (a.cout <= 64) {
-    ph = 16; bn = 64; wm = 4; wn = 1;
-  } else {
-    ph = 8; bn = 128; wm = 2; wn = 2;
-  }
-  snprintf(o, 160, "void nst::k_conv<%s, %d, %d, %d, %d, %d, %d, %s>(nst::ConvArgs, nst::Batch)",
-           precision == 1 ? "__bf16" : "float", ph, bn, wm, wn, in_mode, epi, seg2 ? "true" : "false");
   return o;
 }
 
