@@ -1680,24 +1680,30 @@ __global__ __launch_bounds__(256) void k_content_partial(const float *rc, long l
   if (threadIdx.x == 0) part[g.slot[t] * part_ss + blk] = red[0];
 }
 
-__global__ void k_content_accum(const double *part, long long part_ss, Batch g, double *acc) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  double s = acc[0];
+// acc += the block partials of the batch, tile by tile in tile order: a tile's partials
+// are added by a fixed tree (thread j sums the partials j, j + 256, ... in order, then
+// the 256 sums pairwise), and each tile sum is added to acc in turn.  The order depends
+// only on the tile, not on how tiles are grouped into launches, so any tile batching
+// gives the same bits.
+__global__ __launch_bounds__(256) void k_content_accum(const double *part, long long part_ss, Batch g,
+                                                       double *acc) {
+  __shared__ double red[256];
+  double total = threadIdx.x == 0 ? acc[0] : 0.0;
   for (int t = 0; t < g.n; ++t) {
     const int nb = g.pfx[t + 1] - g.pfx[t];
     const double *p = part + g.slot[t] * part_ss;
-    // in block order; the loads of 32 blocks go out together
-    int b = 0;
-    for (; b + 32 <= nb; b += 32) {
-      double v[32];
-#pragma unroll
-      for (int q = 0; q < 32; ++q) v[q] = p[b + q];
-#pragma unroll
-      for (int q = 0; q < 32; ++q) s += v[q];
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nb; b += 256) s += p[b];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+      __syncthreads();
     }
-    for (; b < nb; ++b) s += p[b];
+    if (threadIdx.x == 0) total += red[0];
+    __syncthreads();   // red is rewritten by the next tile
   }
-  acc[0] = s;
+  if (threadIdx.x == 0) acc[0] = total;
 }
 
 hipError_t launch_content_partial(const float *rc, long long rc_ss, int C, const Batch &g,
@@ -1711,7 +1717,7 @@ hipError_t launch_content_partial(const float *rc, long long rc_ss, int C, const
 
 hipError_t launch_content_accum(const double *part, long long part_ss, const Batch &g,
                                 double *acc, hipStream_t s) {
-  hipLaunchKernelGGL(k_content_accum, dim3(1), dim3(64), 0, s, part, part_ss, g, acc);
+  hipLaunchKernelGGL(k_content_accum, dim3(1), dim3(256), 0, s, part, part_ss, g, acc);
   return hipGetLastError();
 }
 
