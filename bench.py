@@ -10,8 +10,9 @@ receptive-field margin 155 (48 tiles).  The style Grams and content features are
 computed once, untimed; each timed step is nst_loss_grad(STEP1 | STEP2) with all
 inputs resident in HBM.  Step 2 recomputes each tile batch's forward as Algorithm 1
 prints it (memory: one tile batch); the same evaluation with every tile's
-activations resident (NST_RESIDENT) is reported beside it, as are FP32, the smaller
-scales of the content pyramid and the ragged 1000 px tiling of a 3024 x 4032 image.
+activations resident (NST_RESIDENT) is reported beside it, as are the whole image as
+one window (a single tile, which one GPU's HBM holds), FP32, the smaller scales of the
+content pyramid and the ragged 1000 px tiling of a 3024 x 4032 image.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -233,6 +234,8 @@ def main():
     ap.add_argument("--ws-gib", type=float, default=200.0)
     ap.add_argument("--resident-steps", type=int, default=3,
                     help="steps of the same evaluation with every tile's activations resident (0 skips)")
+    ap.add_argument("--one-window-steps", type=int, default=3,
+                    help="steps of the same evaluation with the whole image as one window (0 skips)")
     ap.add_argument("--no-scales", action="store_true", help="skip the pyramid scales and the ragged tiling")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -305,6 +308,19 @@ def main():
         result["resident"] = {"ms_per_step": round(ms_r, 3), "value": round(args.H * args.W / (ms_r * 1e-3) / 1e6, 3),
                               "workspace_gib": round(ev.workspace_gib(), 2),
                               "step2": "reuses Step 1's activations (NST_RESIDENT)"}
+        ev.close()
+
+    if args.one_window_steps > 0:
+        # the whole image as one window: a single tile (no margin inside the image, nothing
+        # recomputed; Step 1 keeps its activations for Step 2), which one GPU's HBM holds
+        T1 = max(args.H, args.W)
+        ev = Eval(args.precision, ws, bs, x, c, s, T1, args.m, resident=True, tile_batch=1, ws_gib=args.ws_gib)
+        ms_w, _, e_w = ev.timed(args.one_window_steps, 1, f"{args.precision} one window")
+        dg = float((g_main.double() - ev.grad.double()).norm() / g_main.double().norm())
+        result["one_window"] = {"ms_per_step": round(ms_w, 3), "value": round(args.H * args.W / (ms_w * 1e-3) / 1e6, 3),
+                                "T": T1, "tiles": 1, "workspace_gib": round(ev.workspace_gib(), 2),
+                                "energy_rel_diff_vs_tiled": abs(e_w[0] - energy[0]) / abs(energy[0]),
+                                "grad_vector_rel_diff_vs_tiled": float("%.4e" % dg)}
         ev.close()
 
     if args.fp32_steps > 0 and args.precision != "fp32":
