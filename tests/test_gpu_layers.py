@@ -20,7 +20,7 @@ stage is checked here on the GPU's own inputs, where no decision can differ:
   activations (same ReLU masks and pool routing), with the BF16 storage points of
   oracle/bf16ref.py for BF16.
 
-Bars (relative; the design doc lists them as readings): FP32 forward ||A - A*|| <= 1e-5 ||A*||
+Bars (relative): FP32 forward ||A - A*|| <= 1e-5 ||A*||
 and max |A - A*| <= 1e-4 rms, Grams <= 1e-6, energies <= 1e-6, gradient <= 1e-5; BF16
 forward every element within one BF16 unit of the reference and at most 1e-3 of the
 elements off by one unit, Grams <= 1e-6, energies <= 1e-5 (content) / 1e-12 (style),
