@@ -158,6 +158,43 @@ def golden_errors(name, energy, grad):
             "grad_samples_vector_rel": float("%.3e" % (np.linalg.norm(gv - ref) / np.linalg.norm(ref)))}
 
 
+def multiscale_runs(args, ws, bs, x, c, s):
+    """Whole style transfers (Algorithm 2): x starts from the content image downscaled to
+    the first of 4 scales; each scale runs its L-BFGS iterations (history 100 at the
+    first scale, 10 after), one loss + gradient evaluation per iteration."""
+    import torch
+    from paper_2212_13459_amd import Context
+    from paper_2212_13459_amd.multiscale import iteration_schedule, style_transfer
+    nst = Context(ws, bs, args.precision, tile_batch=args.tile_batch, ws_limit=int(args.ws_gib * (1 << 30)))
+    dev = torch.device("cuda", 0)
+    c_d, s_d = torch.from_numpy(c).to(dev), torch.from_numpy(s).to(dev)
+    out = {}
+    modes = ["fast", "full"] if args.multiscale == "both" else [args.multiscale]
+    for mode in modes:
+        its = iteration_schedule(4, fast=(mode == "fast"))
+
+        def progress(scale, n, e):
+            if n % 100 == 0:
+                log(f"[bench] multiscale {mode}: scale {scale + 1}, evaluation {n}, E={e:.6e}")
+
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        img, recs = style_transfer(nst, c_d, s_d, n_scales=4, iterations=its, T=args.T, callback=progress)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        log(f"[bench] multiscale {mode}: {dt:.1f} s")
+        out["SPST-fast" if mode == "fast" else "SPST"] = {
+            "seconds": round(dt, 2), "iterations": its,
+            "scales": [{"size": list(r["size"]), "evaluations": r["evaluations"], "seconds": round(r["seconds"], 3),
+                        "E_first": r["E_first"], "E_last": r["E_last"]} for r in recs]}
+        del img
+    nst._ws = {}
+    nst.close()
+    del c_d, s_d
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(args, x, c, s, ws, bs):
     """The FP64 oracle's tiled two-pass evaluation (Algorithm 1) on a bounded sample of
     the workload: Step 1 and Step 2 of the one tile that holds the image centre."""
@@ -237,6 +274,9 @@ def main():
     ap.add_argument("--one-window-steps", type=int, default=3,
                     help="steps of the same evaluation with the whole image as one window (0 skips)")
     ap.add_argument("--no-scales", action="store_true", help="skip the pyramid scales and the ragged tiling")
+    ap.add_argument("--multiscale", default="none", choices=["none", "fast", "full", "both"],
+                    help="also time whole style transfers (Algorithm 2, 4 scales, L-BFGS): SPST-fast "
+                         "(600, 200, 66, 30 iterations), SPST (600, 300, 300, 300) or both")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first launch a plain copy (negation) kernel of this many MiB three times, "
@@ -361,6 +401,9 @@ def main():
                          "oracle_C4": golden_errors("C4", e4, ev.grad)}
             ev.close()
         result["ragged"] = rag
+
+    if args.multiscale != "none":
+        result["multiscale"] = multiscale_runs(args, ws, bs, x, c, s)
 
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(args, x, c, s, ws, bs)
