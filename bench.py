@@ -9,10 +9,11 @@ w = 1/5, content relu4_2 with alpha = 1, tiles of 1024 px with the exact
 receptive-field margin 155 (48 tiles).  The style Grams and content features are
 computed once, untimed; each timed step is nst_loss_grad(STEP1 | STEP2) with all
 inputs resident in HBM.  Step 2 recomputes each tile batch's forward as Algorithm 1
-prints it (memory: one tile batch); the same evaluation with every tile's
-activations resident (NST_RESIDENT) is reported beside it, as are the whole image as
-one window (a single tile, which one GPU's HBM holds), FP32, the smaller scales of the
-content pyramid and the ragged 1000 px tiling of a 3024 x 4032 image.
+prints it (memory: one batch of 24 tiles; batches of 1, 8 and 16 tiles are timed beside it).
+The same evaluation with every tile's activations resident (NST_RESIDENT) is reported
+beside it, as are the whole image as one window (a single tile, which one GPU's HBM
+holds), FP32, the smaller scales of the content pyramid and the ragged 1000 px tiling of
+a 3024 x 4032 image.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -267,7 +268,9 @@ def main():
     ap.add_argument("--sigma", type=float, default=16.0)
     ap.add_argument("--T", type=int, default=1024)
     ap.add_argument("--m", type=int, default=155)
-    ap.add_argument("--tile-batch", type=int, default=32)
+    ap.add_argument("--tile-batch", type=int, default=32, help="tiles per launch at most (48 tiles: 2 batches of 24)")
+    ap.add_argument("--tile-batch-sweep", default="1,8,16",
+                    help="other tile batches timed beside the headline (memory against speed; '' skips)")
     ap.add_argument("--ws-gib", type=float, default=200.0)
     ap.add_argument("--resident-steps", type=int, default=3,
                     help="steps of the same evaluation with every tile's activations resident (0 skips)")
@@ -323,7 +326,7 @@ def main():
         "config": {"workload": f"loss+grad x {args.H}x{args.W}, style {args.Hs}x{args.Ws}, "
                                f"tiles {args.T} px margin {args.m} ({n_tiles} tiles), VGG-19 conv1_1..conv5_1",
                    "H": args.H, "W": args.W, "style_H": args.Hs, "style_W": args.Ws, "T": args.T, "m": args.m,
-                   "tiles": n_tiles, "style_weight": 0.2, "alpha": 1.0,
+                   "tiles": n_tiles, "tile_batch": args.tile_batch, "style_weight": 0.2, "alpha": 1.0,
                    "step2": "recomputes each tile batch's forward (Algorithm 1)",
                    "workspace_gib": round(ev.workspace_gib(), 2)},
         "roofline": roofline(args.precision, stats, args.steps),
@@ -349,6 +352,16 @@ def main():
                               "workspace_gib": round(ev.workspace_gib(), 2),
                               "step2": "reuses Step 1's activations (NST_RESIDENT)"}
         ev.close()
+
+    if args.tile_batch_sweep:
+        sweep = {}
+        for tb in [int(v) for v in args.tile_batch_sweep.split(",") if v]:
+            ev = Eval(args.precision, ws, bs, x, c, s, args.T, args.m, tile_batch=tb, ws_gib=args.ws_gib)
+            ms_b, _, _ = ev.timed(3, 1, f"{args.precision} tile batch {tb}")
+            sweep[str(tb)] = {"ms_per_step": round(ms_b, 3), "value": round(args.H * args.W / (ms_b * 1e-3) / 1e6, 3),
+                              "workspace_gib": round(ev.workspace_gib(), 2)}
+            ev.close()
+        result["tile_batch_sweep"] = sweep
 
     if args.one_window_steps > 0:
         # the whole image as one window: a single tile (no margin inside the image, nothing
