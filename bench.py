@@ -107,10 +107,16 @@ class Eval:
 
 
 def kernel_frac(st, prec):
+    """The kernel's bound from its algorithmic intensity (FLOP per byte) against the ridge
+    point of the MFMA peak over the HBM peak, and its fraction of that bound's peak; both
+    fractions are listed."""
     sec = st["ms"] * 1e-3
-    if st["flops"] > 0:
-        return {"bound": "mfma", "frac": round(st["flops"] / sec / 1e12 / PEAK_TFLOPS[prec], 4)}
-    return {"bound": "hbm", "frac": round(st["bytes"] / sec / 1e9 / HBM_GBS, 4)}
+    mfma = st["flops"] / sec / 1e12 / PEAK_TFLOPS[prec]
+    hbm = st["bytes"] / sec / 1e9 / HBM_GBS
+    ridge = PEAK_TFLOPS[prec] * 1e12 / (HBM_GBS * 1e9)
+    bound = "mfma" if st["bytes"] == 0 or st["flops"] / st["bytes"] >= ridge else "hbm"
+    return {"bound": bound, "frac": round(mfma if bound == "mfma" else hbm, 4),
+            "mfma_frac": round(mfma, 4), "hbm_frac": round(hbm, 4)}
 
 
 def roofline(prec, stats, steps):
