@@ -1079,17 +1079,20 @@ __global__ __launch_bounds__(256, kImgBlocksPerCU<T>) void k_conv_img(ConvArgs a
 }
 
 // k_conv3 tile configurations: BN output channels, WM x WN waves, PH x 16 pixel patches,
-// sa = one halo buffer.  BF16 layers with 256 or 512 channels (long K loops) use 4 waves
-// with 128 x 128 wave tiles (AGPR accumulators, one block and one wave per SIMD).
-// Narrower layers have short K loops (2 to 4 chunks), so per-block set-up and epilogue
-// weigh most: they use one halo buffer and several resident blocks per CU, whose phases
-// overlap: 64-channel tiles with three (52 KB of LDS), BF16 128-channel tiles (4 waves of
-// 128 px x 64 ch) with two (76 KB).  FP32 keeps two waves per SIMD throughout.
+// sa = one halo buffer.  BF16 layers with 256 or 512 output channels and long K loops
+// (K = 9 C_in + C_in2 >= 2304) use 4 waves with 128 x 128 wave tiles (AGPR accumulators,
+// one block and one wave per SIMD).  Shorter K loops (2 to 4 chunks: every 64- and
+// 128-channel layer, conv3_1 with its 128 input channels, the top layer's residual
+// segment alone), where each block's set-up (about 2 us before its first MFMA) and
+// epilogue weigh most, use one halo buffer and several resident blocks per CU, whose
+// phases overlap: 64-channel tiles with three (52 KB of LDS), BF16 128-channel tiles (4
+// waves of 128 px x 64 ch) with two (76 KB).  FP32 keeps two waves per SIMD throughout.
 struct Conv2Cfg { int bn, wm, wn, ph; bool sa; };
-static Conv2Cfg conv2_cfg(int precision, int cout) {
+constexpr int kLongK = 9 * 256;
+static Conv2Cfg conv2_cfg(int precision, int cout, int k = kLongK) {
   if (precision == 1) {
     if (cout <= 64) return {64, 4, 1, 16, true};
-    if (cout % 256 == 0) return {256, 2, 2, 16, false};
+    if (cout % 256 == 0 && k >= kLongK) return {256, 2, 2, 16, false};
     return {128, 2, 2, 16, true};
   }
   if (cout <= 64) return {64, 4, 1, 16, true};
@@ -1121,6 +1124,8 @@ static hipError_t conv_dispatch(int in_mode, int epi, const ConvArgs &a, const B
     return run_conv3<T, 32, 4, 1, 256 / kConvPW, EPI_STITCH, false, false, true>(a, g, s);   // one halo buffer
   }
   const bool small = a.cout <= 64;
+  // BF16: the 256-channel tile for long K loops only (see conv2_cfg)
+  const bool long256 = a.cout % 256 == 0 && 9 * a.cin + (seg2 ? a.cin2 : 0) >= kLongK;
   if (epi == EPI_FWD) {
     if (seg2) return hipErrorInvalidValue;
     if (in_mode == IN_IMAGE) {
@@ -1142,7 +1147,7 @@ static hipError_t conv_dispatch(int in_mode, int epi, const ConvArgs &a, const B
   return a.rc ? run_conv3<T, BN_, WM_, WN_, PH_, EPI_FWD, false, true, SA_>(a, g, s)     \
               : run_conv3<T, BN_, WM_, WN_, PH_, EPI_FWD, false, false, SA_>(a, g, s)
       if (small) NST_CONV3_FWD(64, 4, 1, 16, true);
-      if (a.cout % 256 == 0) NST_CONV3_FWD(256, 2, 2, 16, false);
+      if (long256) NST_CONV3_FWD(256, 2, 2, 16, false);
       NST_CONV3_FWD(128, 2, 2, 16, true);
 #undef NST_CONV3_FWD
     } else {
@@ -1160,11 +1165,11 @@ static hipError_t conv_dispatch(int in_mode, int epi, const ConvArgs &a, const B
     if constexpr (sizeof(T) == 2) {
       if (a.rc) {   // the content residual enters in FP32 (F32E)
         if (small) NST_CONV3_BWD(64, 4, 1, 16, true, true);
-        if (a.cout % 256 == 0) NST_CONV3_BWD(256, 2, 2, 16, true, false);
+        if (long256) NST_CONV3_BWD(256, 2, 2, 16, true, false);
         NST_CONV3_BWD(128, 2, 2, 16, true, true);
       }
       if (small) NST_CONV3_BWD(64, 4, 1, 16, false, true);
-      if (a.cout % 256 == 0) NST_CONV3_BWD(256, 2, 2, 16, false, false);
+      if (long256) NST_CONV3_BWD(256, 2, 2, 16, false, false);
       NST_CONV3_BWD(128, 2, 2, 16, false, true);
     } else {
       if (small) NST_CONV3_BWD(64, 4, 1, 16, false, true);
@@ -1188,7 +1193,7 @@ const char *conv_kernel_name(int precision, int in_mode, int epi, const ConvArgs
     snprintf(o, 160, "void nst::k_conv3<%s, 32, 4, 1, %d, %d, false, false, true>(nst::ConvArgs, nst::Batch)", ty,
              256 / kConvPW, EPI_STITCH);
   } else {
-    const Conv2Cfg k = conv2_cfg(precision, a.cout);
+    const Conv2Cfg k = conv2_cfg(precision, a.cout, 9 * a.cin + (seg2 ? a.cin2 : 0));
     const bool f32e = precision == 1 && a.rc != nullptr;
     snprintf(o, 160, "void nst::k_conv3<%s, %d, %d, %d, %d, %d, %s, %s, %s>(nst::ConvArgs, nst::Batch)", ty, k.bn,
              k.wm, k.wn, k.ph, epi, seg2 ? "true" : "false", f32e ? "true" : "false", k.sa ? "true" : "false");
