@@ -80,6 +80,19 @@ __device__ __forceinline__ int find_tile(const Batch &g, int bid) {
 // Width of the k_conv3 patches (see below); conv1_1 (k_conv_img) keeps 8 x 32.
 constexpr int kConvPW = 16;
 
+// Pixel (within its 32-pixel MFMA operand block) of operand column l32.  A ds_read_b128
+// serves 8 lanes per cycle, lanes {0-3, 20-23}, {4-7, 16-19}, {8-11, 28-31}, {12-15, 24-27}
+// (and the same + 32), over 64 four-byte banks.  With 80-byte halo rows, halo row P starts
+// on bank group 5 P mod 16, so 32 consecutive rows are conflict-free in every cycle.  A
+// block of two 16-pixel patch rows puts its second run at P + 18 instead of P + 16; its
+// columns are rotated by two so that every lane reads a halo row congruent to l32 mod 16,
+// the bank groups of one consecutive run.  Any pixel order is valid as long as the operand
+// reads and the epilogues use the same one.
+template <int PW> __device__ __forceinline__ int blk_pixel(int l32) {
+  if constexpr (PW == 16) return l32 < 16 ? l32 : 16 + ((l32 - 2) & 15);
+  else return l32;
+}
+
 // ---------------------------------------------------------------------------------------
 // Pipelined implicit-GEMM 3x3 convolution (NHWC input) on MFMA.
 //   Work block: a PH x PW output patch (PW = kConvPW = 16, M = PH PW pixels) x BN output
@@ -93,9 +106,9 @@ constexpr int kConvPW = 16;
 //   wave's own loads and passes one barrier.  With one halo buffer (SA) the next chunk's
 //   halo is loaded between chunks instead.
 //   A 32-row MFMA operand block is two patch rows of 16 pixels, i.e. two runs of 16
-//   consecutive LDS rows with a gap between them.  32-wide patches (one run of 32 rows)
-//   read the operand blocks without bank conflicts, but the regions a pass computes are
-//   ragged (e.g. 132-138 px wide at stride 8 for 1024 px tiles): 16 x 16 patches pad the
+//   consecutive LDS rows with a gap between them, read in the column order of blk_pixel
+//   (bank-conflict free like one run of 32 rows).  32-wide patches would need no such
+//   order, but the regions a pass computes are ragged (e.g. 132-138 px wide at stride 8 for 1024 px tiles): 16 x 16 patches pad the
 //   deep layers' MFMA work by 8.0% instead of 9.9% at 6048 x 8064 and measured 3% faster
 //   over the whole evaluation.  Halo-patch rows are
 //   padded to 80 bytes (unit p of a chunk is row p / 5, 16-byte chunk p % 5; chunk 4 is
@@ -129,7 +142,7 @@ __device__ __forceinline__ void load_kstep(KFrag<TM, TN> &f, const T *A, const T
 }
 
 // The weights fragment is the MFMA's first operand: block (tm, tn) accumulates the
-// transposed 32 x 32 tile, channels by pixels, so that lane (l32, half) holds pixel l32 of
+// transposed 32 x 32 tile, channels by pixels, so that lane (l32, half) holds column l32 of
 // the block and channels 8 (r / 4) + 4 half + (r mod 4) in element r: four consecutive
 // channels per group of four elements.
 template <typename T, int TM, int TN>
@@ -180,7 +193,7 @@ __device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(
 template <int BN, int WM, int WN, int PH, int PW, int EPI, int SMEM_BYTES>
 __device__ __forceinline__ void epi_bf16(f32x16 (&acc)[PH * PW / (WM * 32)][BN / (WN * 32)], bf16 *sm,
                                          const ConvArgs &a, long long slot, int y0, int x0, int h, int w, int n0,
-                                         int tid, int wm, int wn, int l32, int half) {
+                                         int tid, int wm, int wn, int lpx, int half) {
   constexpr int BM = PH * PW, NT = WM * WN * 64;
   constexpr int TM = BM / (WM * 32), TN = BN / (WN * 32);
   constexpr int RS = BN + 8;   // row pitch in BF16: 4 mod 64 words for even BN / 32
@@ -190,7 +203,7 @@ __device__ __forceinline__ void epi_bf16(f32x16 (&acc)[PH * PW / (WM * 32)][BN /
   const int cout = a.cout;
   // backward: an optional per-channel constant joins the adjoint before the mask
   const bool bwd_bias = EPI != EPI_FWD && a.bias != nullptr;
-  // phase 1: block (tm, tn), lane: pixel l32, channels 8 jj + 4 half + (0..3) (mma_kstep)
+  // phase 1: block (tm, tn), lane: pixel lpx, channels 8 jj + 4 half + (0..3) (mma_kstep)
 #pragma unroll
   for (int tn = 0; tn < TN; ++tn)
 #pragma unroll
@@ -200,7 +213,7 @@ __device__ __forceinline__ void epi_bf16(f32x16 (&acc)[PH * PW / (WM * 32)][BN /
       if (EPI == EPI_FWD || bwd_bias) b = *(const f32x4 *)(a.bias + (n0 + cl < cout ? n0 + cl : 0));
 #pragma unroll
       for (int tm = 0; tm < TM; ++tm) {
-        const int m = wm * TM * 32 + tm * 32 + l32;
+        const int m = wm * TM * 32 + tm * 32 + lpx;
         u16x4 o;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
@@ -320,7 +333,7 @@ template <typename T, int BN, int WM, int WN, int PH, int PW, int EPI, int SMEM_
 __device__ __forceinline__ void conv_epilogue(f32x16 (&acc)[PH * PW / (WM * 32)][BN / (WN * 32)], T *sm,
                                               const ConvArgs &a, const Batch &g, int t, long long slot,
                                               int y0, int x0, int h, int w, int n0, int tid, int wm, int wn,
-                                              int l32, int half) {
+                                              int lpx, int half) {
   constexpr int BM = PH * PW, NT = WM * WN * 64;
   constexpr int TM = BM / (WM * 32), TN = BN / (WN * 32);
   constexpr int VEC = 16 / sizeof(T), NQ = VEC / 4;
@@ -333,7 +346,7 @@ __device__ __forceinline__ void conv_epilogue(f32x16 (&acc)[PH * PW / (WM * 32)]
   // F32E, so that each kernel holds one epilogue: with both behind a run-time test the
   // compiler copies every accumulator to VGPRs ahead of it and spills)
   if constexpr (sizeof(T) == 2 && !F32E) {
-    epi_bf16<BN, WM, WN, PH, PW, EPI, SMEM_BYTES>(acc, (bf16 *)sm, a, slot, y0, x0, h, w, n0, tid, wm, wn, l32, half);
+    epi_bf16<BN, WM, WN, PH, PW, EPI, SMEM_BYTES>(acc, (bf16 *)sm, a, slot, y0, x0, h, w, n0, tid, wm, wn, lpx, half);
     return;
   }
   float *so = (float *)sm;
@@ -410,14 +423,14 @@ __device__ __forceinline__ void conv_epilogue(f32x16 (&acc)[PH * PW / (WM * 32)]
     // the first group's loads are in flight while the accumulators go to LDS
     if (fwd_rc || bwd_rc || bwd_mask) load_group(0, nc);
     if (p > 0) lds_barrier();
-    // accumulator block (tm, tq): pixel l32, channels 8 jj + 4 half + (0..3) (see mma_kstep)
+    // accumulator block (tm, tq): pixel lpx, channels 8 jj + 4 half + (0..3) (see mma_kstep)
 #pragma unroll
     for (int tm = 0; tm < TM; ++tm)
 #pragma unroll
       for (int tq = 0; tq < TNP; ++tq)
 #pragma unroll
         for (int jj = 0; jj < 4; ++jj) {
-          const int m = wm * TM * 32 + tm * 32 + l32;
+          const int m = wm * TM * 32 + tm * 32 + lpx;
           const f32x16 &av = acc[tm][p * TNP + tq];
           const f32x4 v = {av[4 * jj], av[4 * jj + 1], av[4 * jj + 2], av[4 * jj + 3]};
           *(f32x4 *)(&so[m * RSW + wn * CW + tq * 32 + 8 * jj + 4 * half]) = v;
@@ -765,11 +778,12 @@ __global__ __launch_bounds__(WM * WN * 64, SA ? (BN <= 64 ? 3 : 2) : 1) void k_c
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = wv / WN, wn = wv % WN;
   const int l32 = lane & 31, half = lane >> 5;
+  const int lpx = blk_pixel<PW>(l32);   // this lane's pixel in each operand block
 
   int pidx[TM];
 #pragma unroll
   for (int tm = 0; tm < TM; ++tm) {
-    const int m = wm * TM * 32 + tm * 32 + l32;
+    const int m = wm * TM * 32 + tm * 32 + lpx;
     pidx[tm] = (m / PW) * WP + (m % PW);
   }
   f32x16 acc[TM][TN];
@@ -907,10 +921,10 @@ __global__ __launch_bounds__(WM * WN * 64, SA ? (BN <= 64 ? 3 : 2) : 1) void k_c
   }
   if constexpr (EPI == EPI_STITCH) {
     // image gradient (FP32 CHW) at the owned pixels: channels 0..2 of the padded 32
-    // accumulator element r of lanes 0..31 is channel r of pixel l32 (see mma_kstep)
+    // accumulator element r of lanes 0..31 is channel r of pixel lpx (see mma_kstep)
 #pragma unroll
     for (int tm = 0; tm < TM; ++tm) {
-      const int m = wm * TM * 32 + tm * 32 + l32;
+      const int m = wm * TM * 32 + tm * 32 + lpx;
       const int py = y0 + m / PW, px = x0 + m % PW;
       if (half == 0 && py < ey && px < ex) {
 #pragma unroll
@@ -919,7 +933,7 @@ __global__ __launch_bounds__(WM * WN * 64, SA ? (BN <= 64 ? 3 : 2) : 1) void k_c
       }
     }
   } else {
-    conv_epilogue<T, BN, WM, WN, PH, PW, EPI, SMEM, F32E>(acc, sm, a, g, t, slot, y0, x0, h, w, n0, tid, wm, wn, l32,
+    conv_epilogue<T, BN, WM, WN, PH, PW, EPI, SMEM, F32E>(acc, sm, a, g, t, slot, y0, x0, h, w, n0, tid, wm, wn, lpx,
                                                       half);
   }
 }
