@@ -80,14 +80,15 @@ __device__ __forceinline__ int find_tile(const Batch &g, int bid) {
 // Width of the k_conv3 patches (see below); conv1_1 (k_conv_img) keeps 8 x 32.
 constexpr int kConvPW = 16;
 
-// Pixel (within its 32-pixel MFMA operand block) of operand column l32.  A ds_read_b128
-// serves 8 lanes per cycle, lanes {0-3, 20-23}, {4-7, 16-19}, {8-11, 28-31}, {12-15, 24-27}
-// (and the same + 32), over 64 four-byte banks.  With 80-byte halo rows, halo row P starts
-// on bank group 5 P mod 16, so 32 consecutive rows are conflict-free in every cycle.  A
-// block of two 16-pixel patch rows puts its second run at P + 18 instead of P + 16; its
-// columns are rotated by two so that every lane reads a halo row congruent to l32 mod 16,
-// the bank groups of one consecutive run.  Any pixel order is valid as long as the operand
-// reads and the epilogues use the same one.
+// Pixel (within its 32-pixel MFMA operand block) of operand column l32.  The measured LDS
+// bank conflicts fit a ds_read_b128 that serves 8 lanes per cycle, lanes {0-3, 20-23},
+// {4-7, 16-19}, {8-11, 28-31}, {12-15, 24-27} (and the same + 32), over 64 four-byte
+// banks.  With 80-byte halo rows, halo row P starts on bank group 5 P mod 16, so 32
+// consecutive rows are conflict-free in every cycle.  A block of two 16-pixel patch rows
+// puts its second run at P + 18 instead of P + 16; its columns are rotated by two so that
+// every lane reads a halo row congruent to l32 mod 16, the bank groups of one consecutive
+// run.  Any pixel order is valid as long as the operand reads and the epilogues use the
+// same one.
 template <int PW> __device__ __forceinline__ int blk_pixel(int l32) {
   if constexpr (PW == 16) return l32 < 16 ? l32 : 16 + ((l32 - 2) & 15);
   else return l32;
