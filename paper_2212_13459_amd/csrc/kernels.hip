@@ -1096,9 +1096,9 @@ __global__ __launch_bounds__(256, kImgBlocksPerCU<T>) void k_conv_img(ConvArgs a
 // k_conv3 tile configurations: BN output channels, WM x WN waves, PH x 16 pixel patches,
 // sa = one halo buffer.  BF16 layers with 256 or 512 output channels and long K loops
 // (K = 9 C_in + C_in2 >= 2304) use 4 waves with 128 x 128 wave tiles (AGPR accumulators,
-// one block and one wave per SIMD).  Shorter K loops (2 to 4 chunks: every 64- and
-// 128-channel layer, conv3_1 with its 128 input channels, the top layer's residual
-// segment alone), where each block's set-up (about 2 us before its first MFMA) and
+// one block and one wave per SIMD).  Shorter K loops (K = 576 or 1152: every 64- and
+// 128-channel layer and conv3_1 with its 128 input channels; K = 512: the top layer's
+// residual segment alone), where each block's set-up (about 2 us before its first MFMA) and
 // epilogue weigh most, use one halo buffer and several resident blocks per CU, whose
 // phases overlap: 64-channel tiles with three (52 KB of LDS), BF16 128-channel tiles (4
 // waves of 128 px x 64 ch) with two (76 KB).  FP32 keeps two waves per SIMD throughout.
